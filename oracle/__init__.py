@@ -1,0 +1,17 @@
+"""FP64 CPU oracle for overrelaxation gauge fixing (test infrastructure).
+
+Only the test-suite, the smoke check and the benchmark's CPU-baseline leg may
+import this package. It shares no code with the HIP product path and imports
+nothing from it.
+
+* ``gf_oracle.c`` -- Alg. 1 (overrelaxation with even/odd sites), eqs. (1)-(6),
+  reunitarisation; plain C99 loops in double precision.
+* ``diff.py`` -- the functional F_U[g] as a function of g(x) = exp(S(x)) and its
+  gradient by eigendecomposition (numpy), plus the steepest-descent step of
+  eq. (7).
+"""
+from .core import (  # noqa: F401
+    build, load, quality, divergence_field, staple, su2_solve,
+    subgroup_update, site_update, half_sweep, half_sweep_order, sweep,
+    reunit, fix, parity_of_sites,
+)
