@@ -1,0 +1,253 @@
+#!/usr/bin/env python3
+"""Throughput of checkerboard overrelaxation gauge fixing on one MI355X.
+
+Workload: SU(3) Landau gauge, 48^4 lattice, FP32 links (FP64 staple sums,
+SU(2) solve, reunitarisation and F/theta reductions), seeded synthetic field
+U_mu(x) = h(x) exp(i 0.7 sum_a r_a lambda_a / 2) h(x+mu)^dagger, seed 0,
+omega = 1.7.
+
+One timed step = one check period of Alg. 1: 10 sweeps (even + odd
+half-sweep each, reunitarisation fused into the 10th odd half-sweep) followed
+by the F/theta reduction that gates convergence (host read-back included).
+value = lattice sites x sweeps / wall time of the timed steps.
+
+Also reported: the roofline of the dominant kernel (the half-sweep) from HIP
+events recorded on the context's stream around every half-sweep launch in
+the timed region; the plain FP64 GPU form on the same field; runs to
+theta < 1e-7 in FP32 and FP64; and the FP64 CPU oracle timed on the host on
+one full sweep of the same field.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ["sweep.hip", "su3_device.hpp", "gf_math.hpp", "gf_internal.hpp"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1412_1498_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(profile_name, khash):
+    """HBM bytes per half-sweep launch from a committed rocprofv3 --pmc
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", profile_name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if "=" in line and not line.lstrip().startswith("#"):
+                k, v = line.split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("kernel_hash") != khash:
+        return None
+    try:
+        return float(vals["hbm_bytes_per_dispatch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50, help="timed check periods")
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--dims", default="48,48,48,48")
+    ap.add_argument("--amp", type=float, default=0.7)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--omega", type=float, default=1.7)
+    ap.add_argument("--sweeps-per-step", type=int, default=10)
+    ap.add_argument("--storage", type=int, choices=[18, 12], default=18)
+    ap.add_argument("--lps", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--nontemporal", type=int, default=0)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-convergence", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also launch one plain 1 GiB device copy (counter scale reference)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1412_1498_amd import gf, synth
+
+    dims = tuple(int(x) for x in args.dims.split(","))
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    spp = args.sweeps_per_step
+    storage = gf.STORE_12 if args.storage == 12 else gf.STORE_18
+    log(f"generating {dims} amp {args.amp} seed {args.seed} (FP64, on the GPU)")
+    t = time.perf_counter()
+    U64 = synth.random_gauge_field(dims, args.amp, args.seed, device="cuda")
+    torch.cuda.synchronize()
+    log(f"generated in {time.perf_counter() - t:.1f} s")
+
+    def params(prec, timing):
+        return gf.default_params(prec, check_every=spp, reunit_every=10, storage=storage,
+                                 lanes_per_site=args.lps, block_threads=args.block,
+                                 nontemporal=args.nontemporal, timing=timing)
+
+    def timed_run(prec):
+        ctx = gf.Context(dims, gauge=gf.LANDAU, prec=prec, params=params(prec, 1))
+        U = ctx.pack(U64 if prec == gf.F64 else U64.to(torch.complex64))
+        F0, th0 = ctx.quality(U)
+        for _ in range(args.warmup):
+            ctx.sweeps(U, args.omega, spp)
+            ctx.quality(U)
+        ctx.timing()  # discard warm-up launches
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            ctx.sweeps(U, args.omega, spp)
+            F, th = ctx.quality(U)
+            if k % 10 == 9:
+                log(f"{'fp64' if prec == gf.F64 else 'fp32'} step {k + 1}/{args.steps} F {F:.9f} theta {th:.3e}")
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms, nl = ctx.timing()
+        sched = ctx.schedule()
+        del U, ctx
+        torch.cuda.empty_cache()
+        return dict(wall=wall, kernel_ms=ms, launches=nl, F=F, theta=th, F0=F0, theta0=th0, schedule=sched)
+
+
+    def roofline(res, prec):
+        lb = args.storage * (4 if prec == gf.F32 else 8)  # bytes of one stored link
+        per_site = 16 * lb                                # 8 links read + 8 written per site update
+        per_launch = per_site * (V // 2)
+        avg = res["kernel_ms"] / 1e3 / res["launches"]
+        ach = per_launch / avg / 1e9
+        return dict(bytes_per_site_update=per_site, bytes_per_launch=per_launch,
+                    avg_launch_s=avg, achieved_gbs=ach)
+
+    log("timed FP32 run")
+    r32 = timed_run(gf.F32)
+    rf32 = roofline(r32, gf.F32)
+    value = V * spp * args.steps / r32["wall"]
+    khash = kernel_hash()
+    traffic = measured_traffic(f"halfsweep_{'x'.join(map(str, dims))}_f32_{args.storage}real_pmc.txt", khash)
+
+    out = {
+        "metric": "site-sweeps/s (SU(3) OR, 48^4 FP32) + % HBM roofline vs FP64 at theta<1e-7",
+        "value": value,
+        "unit": "site-sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["wall"] / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"SU(3) Landau overrelaxation gauge fixing, {'x'.join(map(str, dims))} lattice, "
+                        f"FP32 links ({args.storage}-real storage), amp {args.amp}, seed {args.seed}, "
+                        f"omega {args.omega}; step = {spp} sweeps + F/theta check, reunitarisation every 10 sweeps",
+            "lattice": list(dims),
+            "sweeps_per_step": spp,
+            "schedule": r32["schedule"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": rf32["achieved_gbs"],
+            "peak": PEAK_HBM_GBS,
+            "unit": "GB/s",
+            "frac": rf32["achieved_gbs"] / PEAK_HBM_GBS,
+            "traffic": traffic,
+            "kernel": "k_half_sweep (one half-sweep: V/2 site updates)",
+            "algorithmic_bytes_per_launch": rf32["bytes_per_launch"],
+            "avg_launch_us": rf32["avg_launch_s"] * 1e6,
+            "launches_timed": r32["launches"],
+            "kernel_source_hash": khash,
+        },
+    }
+
+    if not args.no_fp64:
+        log("timed FP64 run (plain FP64 GPU form)")
+        r64 = timed_run(gf.F64)
+        rf64 = roofline(r64, gf.F64)
+        out["fp64"] = {
+            "value": V * spp * args.steps / r64["wall"],
+            "unit": "site-sweeps/s",
+            "achieved_gbs": rf64["achieved_gbs"],
+            "frac": rf64["achieved_gbs"] / PEAK_HBM_GBS,
+            "avg_launch_us": rf64["avg_launch_s"] * 1e6,
+            "schedule": r64["schedule"],
+        }
+        out["fp32_over_fp64_throughput"] = value / out["fp64"]["value"]
+
+    if not args.no_convergence:
+        conv = {}
+        for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
+            log(f"{name} run to theta < 1e-7")
+            ctx = gf.Context(dims, gauge=gf.LANDAU, prec=prec, params=params(prec, 0))
+            U = ctx.pack(U64 if prec == gf.F64 else U64.to(torch.complex64))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.fix(U, args.omega, 1e-7, 20000)
+            torch.cuda.synchronize()
+            conv[name] = dict(seconds=time.perf_counter() - t0, sweeps=r["iters"], converged=r["converged"],
+                              F=r["F"], theta=r["theta"])
+            del U, ctx
+            torch.cuda.empty_cache()
+        conv["fp32_speedup_to_theta_1e-7"] = conv["fp64"]["seconds"] / conv["fp32"]["seconds"]
+        conv["abs_F_fp32_minus_fp64"] = abs(conv["fp32"]["F"] - conv["fp64"]["F"])
+        conv["theta_convention"] = "literal eq. (3): A = M - M^+, minus trace/3, no 1/2 or 1/(2i)"
+        out["convergence"] = conv
+
+    if args.copy_probe:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * a.numel() * 4
+
+    if not args.no_cpu_baseline:
+        import oracle
+        log("CPU oracle: one full FP64 sweep of the same field on the host")
+        Uh = U64.cpu().numpy()
+        del U64
+        torch.cuda.empty_cache()
+        t0 = time.perf_counter()
+        oracle.sweep(Uh, dims, args.omega)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": V / dt,
+            "unit": "site-sweeps/s",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": f"one full sweep (even + odd half-sweep) of the same {'x'.join(map(str, dims))} field "
+                      f"in FP64 by the single-threaded C oracle, {dt:.1f} s",
+        }
+        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

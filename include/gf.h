@@ -1,0 +1,225 @@
+/*
+ * gf.h -- C ABI of libgf, an MI355X (gfx950) library for Landau and Coulomb
+ * gauge fixing of SU(3) lattice gauge fields by checkerboard overrelaxation.
+ *
+ * Method: N. Cardoso, "Coulomb and Landau Gauge Fixing in GPUs using CUDA and
+ * MILC", Lattice 2014 (arXiv:1412.1498). The functional F_U[g] of eq. (1) is
+ * maximised site by site: at each site the staple K(x) of eq. (5) is built,
+ * the local SU(2) problem of eq. (6) is solved in each of the three SU(2)
+ * subgroups of SU(3), the solution g is over-relaxed to g^omega and applied
+ * to the eight links touching the site (Alg. 1). The quality theta of
+ * eqs. (2)-(3) gates convergence.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Lattice dims are {nx, ny, nz, nt}; every dim must be even and >= 2.
+ *   Directions mu = 0,1,2,3 run along x,y,z,t; boundaries are periodic.
+ * - Site parity p = (x + y + z + t) mod 2; even sites (p = 0) are updated
+ *   first in each sweep.
+ * - Landau gauge uses mu = 0..3 in F, K and theta; Coulomb uses mu = 0..2
+ *   (t is the temporal direction), but g(x) still rotates the temporal
+ *   links. F is normalised by the number d of directions it sums (4 or 3), so
+ *   F = 1 for the unit field. theta uses Delta(x) literally as in eq. (3):
+ *   A = M - M^dagger, M = sum_nu [U_nu(x - nu) - U_nu(x)], minus (Tr A/3) 1.
+ * - g^omega is the exact principal power of the SU(2) solution; subgroups
+ *   are visited in the order (0,1), (0,2), (1,2).
+ * - Precision: GF_F64 stores and updates links in double. GF_F32 stores and
+ *   updates links in float, while the staple sums, the SU(2) solve with its
+ *   power, reunitarisation and the F/theta reductions run in double.
+ * - Field pointers (U) are caller-owned DEVICE pointers, at least 256-byte
+ *   aligned (a torch tensor's data_ptr()), in the internal layout below. The
+ *   library never allocates, frees or keeps them beyond a call.
+ * - Internal link layout (section "Implementation" of the paper): even and
+ *   odd sites are stored separately and each matrix element has its own
+ *   array. The complex element (row r, col c), e = 3r + c, of U_mu(x) sits at
+ *       e * 4V + mu * V + p * V/2 + h,   h = (x + nx(y + ny(z + nz t))) / 2
+ *   in units of one complex (float2 for F32, double2 for F64). With 12-real
+ *   storage (gf_params.storage = GF_STORE_12) only e = 0..5 (rows 0 and 1)
+ *   are stored and row 2 is rebuilt as conj(row0 x row1).
+ * - Canonical layout (pack/unpack only): [t][z][y][x][mu][row][col] complex
+ *   in the context's precision.
+ * - All work is enqueued on the context's HIP stream (the stream handle passed
+ *   at creation; NULL = the default stream). Functions that return results to
+ *   the host synchronise that stream; the others are asynchronous.
+ * - Status codes: negative values are errors; no exception or abort crosses
+ *   this ABI. After an error, gf_last_error() describes it.
+ * - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef GF_H
+#define GF_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GF_OK 0
+#define GF_NOT_CONVERGED 1  /* informational: max_iter reached with theta >= eps */
+#define GF_EINVAL (-1)      /* invalid argument; nothing was enqueued */
+#define GF_ENOMEM (-2)      /* device or pinned host allocation failed */
+#define GF_EDEVICE (-3)     /* a HIP call failed; gf_last_error() has its message */
+#define GF_ENONFINITE (-4)  /* F or theta came out NaN or infinite */
+#define GF_EUNSUPPORTED (-5)/* e.g. nc != 3 */
+
+enum gf_gauge { GF_LANDAU = 0, GF_COULOMB = 1 };
+enum gf_prec { GF_F64 = 0, GF_F32 = 1 };
+enum gf_storage { GF_STORE_18 = 0, GF_STORE_12 = 1 };
+
+typedef struct gf_ctx gf_ctx;
+
+/* Tunables and driver options. Zero-initialise or call gf_params_default. */
+typedef struct gf_params {
+    int check_every;        /* sweeps between F/theta evaluations in the fix
+                               drivers (>= 1); default 1 */
+    int reunit_every;       /* reunitarise every link after each sweep whose
+                               global index is a multiple of this; 0 = never.
+                               Default 20 (F64) / 10 (F32). Fused into the odd
+                               half-sweep, so it costs no extra memory traffic */
+    long long start_sweep;  /* global index of the last sweep already done
+                               (sets the reunitarisation phase on resume) */
+    int storage;            /* GF_STORE_18 (default) or GF_STORE_12 */
+    int lanes_per_site;     /* 0 = default, else 1, 2, 4 or 8 lanes per site */
+    int block_threads;      /* 0 = default, else 64, 128, 192 or 256 */
+    int nontemporal;        /* 1 = streaming (non-temporal) link loads/stores */
+    int use_graph;          /* 1 = replay each check period as a hipGraph */
+    int timing;             /* 1 = time every half-sweep with hipEvents */
+} gf_params;
+
+/* Fill *p with the defaults for precision prec. */
+void gf_params_default(gf_params *p, int prec);
+
+/* Create a context for one lattice. dims = {nx, ny, nz, nt}; nc must be 3;
+ * gauge is GF_LANDAU or GF_COULOMB; prec is GF_F64 or GF_F32; stream is a
+ * hipStream_t (NULL = default stream); p may be NULL for defaults.
+ * Returns GF_EINVAL for odd or non-positive dims or a bad enum,
+ * GF_EUNSUPPORTED for nc != 3, GF_ENOMEM / GF_EDEVICE on allocation failure
+ * (then *out is NULL). On success the context owns its reduction scratch. */
+int gf_create(gf_ctx **out, const int dims[4], int nc, int gauge, int prec, void *stream,
+              const gf_params *p);
+
+/* Create a context for an ensemble of n lattices fixed together (each with
+ * its own dims[4*i..4*i+3] and gauge[i]; common precision and storage).
+ * The single-lattice entry points require n == 1; the gf_batch_* ones
+ * accept any n >= 1. */
+int gf_batch_create(gf_ctx **out, int n, const int *dims, const int *gauge, int prec, void *stream,
+                    const gf_params *p);
+
+/* Release a context (waits for its stream). NULL is accepted. */
+int gf_destroy(gf_ctx *ctx);
+
+/* Human-readable description of the last error on ctx ("" if none). */
+const char *gf_last_error(const gf_ctx *ctx);
+
+/* Bytes of one field of member i in the internal layout:
+ * nelem * 4V * sizeof(complex), nelem = 9 (18-real) or 6 (12-real). */
+size_t gf_field_bytes(const gf_ctx *ctx, int member);
+
+/* Convert member 0's field between the canonical layout U_aos (device) and
+ * the internal layout U (device). 12-real storage drops row 2 on pack and
+ * rebuilds it on unpack. Asynchronous. */
+int gf_pack(gf_ctx *ctx, const void *U_aos, void *U);
+int gf_unpack(gf_ctx *ctx, const void *U, void *U_aos);
+
+/* One half-sweep of Alg. 1 (all sites of one parity, three subgroups each,
+ * over-relaxation parameter omega in (0, 2)) on member 0. No
+ * reunitarisation, no sweep counter change. Asynchronous. */
+int gf_sweep(gf_ctx *ctx, void *U, int parity, double omega);
+
+/* nsweeps full sweeps (even then odd half-sweep) on member 0, reunitarising
+ * on the schedule of gf_params.reunit_every and advancing the context's
+ * sweep counter. Asynchronous. */
+int gf_sweeps(gf_ctx *ctx, void *U, double omega, int nsweeps);
+
+/* Reunitarise every link of member 0 (Gram-Schmidt on rows 0, 1 in double,
+ * row 2 = conj(row0 x row1)). Asynchronous. */
+int gf_reunit(gf_ctx *ctx, void *U);
+
+/* F (eq. 1, on the current field) and theta (eq. 2) of member 0, reduced in
+ * double in a fixed order (bitwise reproducible for a given field).
+ * Synchronises the stream. Returns GF_ENONFINITE if either is NaN or Inf. */
+int gf_quality(gf_ctx *ctx, const void *U, double *F, double *theta);
+
+/* Alg. 1 on member 0: compute F, theta; while theta >= eps and fewer than
+ * max_iter sweeps were done: sweep (with scheduled reunitarisation) and
+ * recompute F, theta every check_every sweeps and after the last allowed
+ * sweep. *iters = sweeps done (0 if the initial theta < eps). Returns GF_OK
+ * if theta < eps, GF_NOT_CONVERGED if max_iter was reached, or an error. */
+int gf_fix(gf_ctx *ctx, void *U, double omega, double eps, int max_iter, int *iters, double *F,
+           double *theta);
+
+/* Alg. 1 on every member of an ensemble at once. U[i] is member i's field,
+ * omega[i] its over-relaxation parameter. Each member stops sweeping as soon
+ * as its own theta < eps at a check; results are bitwise those of gf_fix on
+ * the member alone with the same parameters and schedule. iters, F, theta
+ * are arrays of n. Returns GF_OK if every member converged, else
+ * GF_NOT_CONVERGED (or an error). */
+int gf_batch_fix(gf_ctx *ctx, void *const *U, const double *omega, double eps, int max_iter,
+                 int *iters, double *F, double *theta);
+
+/* F and theta of every member (arrays of n). Synchronises. */
+int gf_batch_quality(gf_ctx *ctx, void *const *U, double *F, double *theta);
+
+/* Time the candidate schedules (lanes per site, workgroup size,
+ * non-temporal access) on a scratch copy of the members' fields U[i] and
+ * keep the fastest in ctx. Every schedule gives bitwise the same links. If
+ * cache_path is not NULL, a previous result for the same device, precision,
+ * storage and lattice list is reused and new results are appended.
+ * Allocates (and frees) a scratch copy of the fields. Synchronises. */
+int gf_autotune(gf_ctx *ctx, void *const *U, double omega, const char *cache_path);
+
+/* The schedule in use: lanes per site, workgroup threads and the
+ * non-temporal flag. */
+int gf_get_schedule(const gf_ctx *ctx, int *lanes_per_site, int *block_threads, int *nontemporal);
+
+/* Total device time (ms) and number of the half-sweep launches timed since
+ * the last call (needs gf_params.timing = 1). Synchronises. */
+int gf_timing(gf_ctx *ctx, double *ms, long long *launches);
+
+/* Set / read the global sweep counter (reunitarisation phase). */
+int gf_set_sweep_count(gf_ctx *ctx, long long sweeps_done);
+long long gf_get_sweep_count(const gf_ctx *ctx);
+
+/* ---- differentiation: F as a function of a gauge transformation ------
+ * g(x) = exp(S(x)), S(x) = i sum_a s_a(x) lambda_a / 2 (Gell-Mann lambda_a,
+ * Tr lambda_a lambda_b = 2 delta_ab). s is a DEVICE array of 8*V reals of
+ * the context precision in layout [a][p][h] (a = generator, p, h as for the
+ * links). */
+
+/* Convert s between the canonical layout [t][z][y][x][a] and [a][p][h]. */
+int gf_pack_alg(gf_ctx *ctx, const void *s_aos, void *s);
+int gf_unpack_alg(gf_ctx *ctx, const void *s, void *s_aos);
+
+/* F_U[g] of eq. (1) for g = exp(S(s)) (U itself is not modified).
+ * Synchronises. */
+int gf_functional(gf_ctx *ctx, const void *U, const void *s, double *F);
+
+/* grad[a][p][h] = dF * dF_U[g]/ds_a(x) at s: the su(3)-valued gradient of
+ * eq. (1) with respect to the gauge transformation. Asynchronous. */
+int gf_functional_grad(gf_ctx *ctx, const void *U, const void *s, double dF, void *grad);
+
+/* Apply g = exp(S(s)): U_mu(x) <- g(x) U_mu(x) g(x + mu)^dagger for all mu.
+ * Asynchronous. */
+int gf_gauge_transform(gf_ctx *ctx, void *U, const void *s);
+
+/* ---- host-only checks (no device use) -----------------------------------
+ * The SU(2) step of the sweep kernels evaluated on the host with the same
+ * code: b = quaternion part (b0, b1, b2, b3) of a staple block, omega the
+ * over-relaxation parameter; r receives g^omega as a quaternion (see the
+ * conventions above). */
+void gf_host_su2_step(const double b[4], double omega, double r[4]);
+
+/* The kernels' own double-precision sine/cosine (valid for x in [0, 2 pi])
+ * and arctangent: out = {sin x, cos x, atan2(y, x)}. */
+void gf_host_trig(double x, double y, double out[3]);
+
+/* Index check: complex-element offsets (element e = 0) of the eight links that the site
+ * (parity, h) of a dims lattice updates in a half-sweep: out[0..3] =
+ * U_mu(x), out[4..7] = U_mu(x - mu). Returns GF_EINVAL for bad arguments. */
+int gf_site_links(const int dims[4], int parity, long long h, long long out[8]);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF_H */

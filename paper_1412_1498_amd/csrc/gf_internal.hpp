@@ -1,0 +1,125 @@
+// gf_internal.hpp -- lattice geometry, per-member descriptors and kernel
+// launchers shared by the HIP translation units of libgf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gf {
+
+// Geometry of one lattice in the even/odd, element-major link layout
+// (section "Implementation"): complex element e of U_mu at site (p, h) lives
+// at e*es + mu*V + p*Vh + h.
+struct Geom {
+    int nx, ny, nz, nt;
+    int hx;         // nx / 2
+    int Vh;         // V / 2 (sites of one parity)
+    int V;          // sites
+    int sz;         // hx * ny       (half-index stride of one z step)
+    int st;         // hx * ny * nz  (half-index stride of one t step)
+    long long es;   // 4V: element stride in complex units
+};
+
+inline Geom make_geom(const int d[4]) {
+    Geom g;
+    g.nx = d[0]; g.ny = d[1]; g.nz = d[2]; g.nt = d[3];
+    g.hx = d[0] / 2;
+    g.V = d[0] * d[1] * d[2] * d[3];
+    g.Vh = g.V / 2;
+    g.sz = g.hx * d[1];
+    g.st = g.sz * d[2];
+    g.es = 4LL * g.V;
+    return g;
+}
+
+// Coordinates of site (p, h) and the half indices of its four backward
+// neighbours x - mu (which have parity 1 - p).
+struct SiteNbr {
+    int hb[4];
+};
+
+__host__ __device__ inline SiteNbr site_neighbours(const Geom &g, int p, int h) {
+    int q = h / g.hx;             // row index j + ny (k + nz t)
+    int ih = h - q * g.hx;
+    int q2 = q / g.ny;
+    int j = q - q2 * g.ny;
+    int t = q2 / g.nz;
+    int k = q2 - t * g.nz;
+    int b = (p + j + k + t) & 1;  // x = 2 ih + b
+    SiteNbr n;
+    n.hb[0] = (ih == 0 && b == 0) ? h + g.hx - 1 : h - 1 + b;
+    n.hb[1] = (j == 0) ? h + (g.ny - 1) * g.hx : h - g.hx;
+    n.hb[2] = (k == 0) ? h + (g.nz - 1) * g.sz : h - g.sz;
+    n.hb[3] = (t == 0) ? h + (g.nt - 1) * g.st : h - g.st;
+    return n;
+}
+
+// Half indices of the four forward neighbours x + mu (parity 1 - p).
+__host__ __device__ inline SiteNbr site_fwd_neighbours(const Geom &g, int p, int h) {
+    int q = h / g.hx;
+    int ih = h - q * g.hx;
+    int q2 = q / g.ny;
+    int j = q - q2 * g.ny;
+    int t = q2 / g.nz;
+    int k = q2 - t * g.nz;
+    int b = (p + j + k + t) & 1;
+    SiteNbr n;
+    n.hb[0] = (ih == g.hx - 1 && b == 1) ? h - g.hx + 1 : h + b;
+    n.hb[1] = (j == g.ny - 1) ? h - (g.ny - 1) * g.hx : h + g.hx;
+    n.hb[2] = (k == g.nz - 1) ? h - (g.nz - 1) * g.sz : h + g.sz;
+    n.hb[3] = (t == g.nt - 1) ? h - (g.nt - 1) * g.st : h + g.st;
+    return n;
+}
+
+// Half index and parity of the canonical site (x, y, z, t).
+__host__ __device__ inline void site_to_ph(const Geom &g, int x, int y, int z, int t, int &p, int &h) {
+    p = (x + y + z + t) & 1;
+    h = (x + g.nx * (y + g.ny * (z + g.nz * t))) >> 1;
+}
+
+// One member of an ensemble as seen by the kernels.
+struct CfgDesc {
+    Geom g;
+    void *U;         // device field in the internal layout
+    double omega;    // over-relaxation parameter
+    int gauge;       // 0 Landau, 1 Coulomb
+    int tile0;       // first sweep tile of this member
+    int qtile0;      // first quality tile of this member
+    int nqtiles;     // quality tiles of this member
+};
+
+// Sites handled by one quality workgroup (fixed, so F and theta are
+// bitwise independent of the sweep schedule).
+constexpr int QTILE = 256;
+
+struct Schedule {
+    int lps;        // lanes per site: 1, 2, 4, 8
+    int block;      // threads per workgroup
+    int nt;         // non-temporal loads/stores
+};
+
+// ---- launchers (defined in the .hip files) ----
+hipError_t launch_half_sweep(int prec, int nelem, const Schedule &s, const CfgDesc *d_desc,
+                             const int *d_tile_cfg, const int *d_active, int ntiles, int parity,
+                             int reunit, hipStream_t st);
+hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int *d_qtile_cfg,
+                          const int *d_active, int nqtiles, double *d_partials, hipStream_t st);
+hipError_t launch_quality_final(const CfgDesc *d_desc, int n, const double *d_partials,
+                                double *d_result, int *d_active, int *d_iters, int swept,
+                                double eps, int update_active, hipStream_t st);
+hipError_t launch_pack(int prec, int nelem, const Geom &g, const void *aos, void *U, int unpack,
+                       hipStream_t st);
+hipError_t launch_reunit(int prec, int nelem, const Geom &g, void *U, hipStream_t st);
+hipError_t launch_pack_alg(int prec, const Geom &g, const void *aos, void *s, int unpack,
+                           hipStream_t st);
+hipError_t launch_expS(int prec, const Geom &g, const void *s, void *gfield, hipStream_t st);
+hipError_t launch_functional(int prec, int nelem, int gauge, const Geom &g, const void *U,
+                             const void *gfield, double *d_partials, hipStream_t st);
+hipError_t launch_functional_grad(int prec, int nelem, int gauge, const Geom &g, const void *U,
+                                  const void *s, const void *gfield, double scale, void *grad,
+                                  hipStream_t st);
+hipError_t launch_gauge_transform(int prec, int nelem, const Geom &g, void *U, const void *gfield,
+                                  hipStream_t st);
+hipError_t launch_sum_partials(const double *d_partials, int n, double *d_out, hipStream_t st);
+
+}  // namespace gf

@@ -1,0 +1,362 @@
+// grad.hip -- F_U[g] of eq. (1) as a function of a gauge transformation
+// g(x) = exp(S(x)), S = i sum_a s_a lambda_a / 2, its gradient with respect to
+// s_a(x), and the application of g to the links.
+//
+// Gradient: F depends on g(x) through (1/(d N_c V)) Re Tr[g(x) K(x)] with
+// K(x) = sum_mu [U_mu(x) g(x+mu)^dagger + U_mu(x-mu)^dagger g(x-mu)^dagger]
+// (eq. 5). With dg/ds_a = e^S sum_k (-ad_S)^k (X_a) / (k+1)!, X_a = i lambda_a/2,
+// and Tr[ad_S(A) B] = -Tr[A ad_S(B)], the gradient is
+//     dF/ds_a(x) = (1/(d N_c V)) Re Tr[X_a Psi],  Psi = sum_k ad_S^k(K e^S)/(k+1)!,
+// one series on a 3x3 matrix per site followed by eight traces. At s = 0 it
+// reduces to Re Tr[X_a K(x)] / (d N_c V).
+#include "su3_device.hpp"
+
+namespace gf {
+
+struct DMat {
+    double re[9], im[9];
+};
+
+__device__ __forceinline__ void dm_mul(const DMat &a, const DMat &b, DMat &c) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            double r = 0.0, m = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                r += a.re[3 * i + k] * b.re[3 * k + j] - a.im[3 * i + k] * b.im[3 * k + j];
+                m += a.re[3 * i + k] * b.im[3 * k + j] + a.im[3 * i + k] * b.re[3 * k + j];
+            }
+            c.re[3 * i + j] = r;
+            c.im[3 * i + j] = m;
+        }
+}
+
+// a * b^dagger
+__device__ __forceinline__ void dm_mul_nd(const DMat &a, const DMat &b, DMat &c) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            double r = 0.0, m = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                r += a.re[3 * i + k] * b.re[3 * j + k] + a.im[3 * i + k] * b.im[3 * j + k];
+                m += a.im[3 * i + k] * b.re[3 * j + k] - a.re[3 * i + k] * b.im[3 * j + k];
+            }
+            c.re[3 * i + j] = r;
+            c.im[3 * i + j] = m;
+        }
+}
+
+// a^dagger * b^dagger
+__device__ __forceinline__ void dm_mul_dd(const DMat &a, const DMat &b, DMat &c) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            double r = 0.0, m = 0.0;
+#pragma unroll
+            for (int k = 0; k < 3; k++) {
+                // conj(a_ki) conj(b_jk)
+                r += a.re[3 * k + i] * b.re[3 * j + k] - a.im[3 * k + i] * b.im[3 * j + k];
+                m -= a.re[3 * k + i] * b.im[3 * j + k] + a.im[3 * k + i] * b.re[3 * j + k];
+            }
+            c.re[3 * i + j] = r;
+            c.im[3 * i + j] = m;
+        }
+}
+
+// S = i sum_a s_a lambda_a / 2 (anti-hermitian, traceless).
+__device__ __forceinline__ void algebra_matrix(const double s[8], DMat &S) {
+    const double r3 = 0.57735026918962576451;  // 1/sqrt(3)
+    // H = sum_a s_a lambda_a / 2 (hermitian), S = i H
+    double hr[9], hi[9];
+    hr[0] = 0.5 * (s[2] + r3 * s[7]);       hi[0] = 0.0;
+    hr[4] = 0.5 * (-s[2] + r3 * s[7]);      hi[4] = 0.0;
+    hr[8] = -r3 * s[7];                     hi[8] = 0.0;
+    hr[1] = 0.5 * s[0];  hi[1] = -0.5 * s[1];
+    hr[3] = 0.5 * s[0];  hi[3] = 0.5 * s[1];
+    hr[2] = 0.5 * s[3];  hi[2] = -0.5 * s[4];
+    hr[6] = 0.5 * s[3];  hi[6] = 0.5 * s[4];
+    hr[5] = 0.5 * s[5];  hi[5] = -0.5 * s[6];
+    hr[7] = 0.5 * s[5];  hi[7] = 0.5 * s[6];
+#pragma unroll
+    for (int e = 0; e < 9; e++) { S.re[e] = -hi[e]; S.im[e] = hr[e]; }
+}
+
+// exp(S) by scaling and squaring of a degree-16 Taylor polynomial (scaled
+// argument of Frobenius norm <= 1/2).
+__device__ void dm_exp(const DMat &S, DMat &E) {
+    double nrm2 = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; e++) nrm2 += S.re[e] * S.re[e] + S.im[e] * S.im[e];
+    const double nrm = sqrt(nrm2);
+    int k = 0;
+    if (nrm > 0.5) k = (int)ceil(log2(nrm / 0.5));
+    const double sc = ldexp(1.0, -k);
+    DMat Y;
+#pragma unroll
+    for (int e = 0; e < 9; e++) { Y.re[e] = S.re[e] * sc; Y.im[e] = S.im[e] * sc; }
+#pragma unroll
+    for (int e = 0; e < 9; e++) { E.re[e] = (e % 4 == 0) ? 1.0 : 0.0; E.im[e] = 0.0; }
+    for (int j = 16; j >= 1; j--) {
+        DMat T;
+        dm_mul(Y, E, T);
+        const double inv = 1.0 / j;
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            E.re[e] = ((e % 4 == 0) ? 1.0 : 0.0) + T.re[e] * inv;
+            E.im[e] = T.im[e] * inv;
+        }
+    }
+    for (int i = 0; i < k; i++) {
+        DMat T;
+        dm_mul(E, E, T);
+        E = T;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void load_s(const R *__restrict__ s, int V, int n, double out[8]) {
+#pragma unroll
+    for (int a = 0; a < 8; a++) out[a] = (double)s[(long long)a * V + n];
+}
+
+template <typename R>
+__device__ __forceinline__ void load_g(const typename V2<R>::type *__restrict__ gf, int V, int n, DMat &m) {
+#pragma unroll
+    for (int e = 0; e < 9; e++) {
+        typename V2<R>::type v = gf[(long long)e * V + n];
+        m.re[e] = v.x;
+        m.im[e] = v.y;
+    }
+}
+
+template <typename R, int NE>
+__device__ __forceinline__ void load_u(const typename V2<R>::type *__restrict__ U, long long es, int off, DMat &m) {
+    Mat<R> t;
+    load_link<R, NE, false>(t, as_global((const void *)U), es, off);
+#pragma unroll
+    for (int e = 0; e < 9; e++) { m.re[e] = t.re[e]; m.im[e] = t.im[e]; }
+}
+
+// g field (9 complex per site, layout [e][p][h]) from s.
+template <typename R>
+__global__ void k_expS(Geom g, const R *__restrict__ s, typename V2<R>::type *__restrict__ gf) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.V) return;
+    double sv[8];
+    load_s(s, g.V, n, sv);
+    DMat S, E;
+    algebra_matrix(sv, S);
+    dm_exp(S, E);
+#pragma unroll
+    for (int e = 0; e < 9; e++) {
+        typename V2<R>::type v;
+        v.x = (R)E.re[e];
+        v.y = (R)E.im[e];
+        gf[(long long)e * g.V + n] = v;
+    }
+}
+
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double sh[16];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m);
+    const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (lane == 0) sh[wid] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; w++) t += sh[w];
+    return t;
+}
+
+// Per-workgroup partial sums of Re Tr[g(x) U_mu(x) g(x+mu)^dagger].
+template <typename R, int NE>
+__global__ void k_functional(Geom g, int nd, const typename V2<R>::type *__restrict__ U,
+                             const typename V2<R>::type *__restrict__ gf, double *__restrict__ part) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    double f = 0.0;
+    if (n < g.V) {
+        const int p = n >= g.Vh, h = n - p * g.Vh;
+        const SiteNbr fw = site_fwd_neighbours(g, p, h);
+        DMat gx;
+        load_g<R>(gf, g.V, n, gx);
+        for (int mu = 0; mu < nd; mu++) {
+            DMat u, gu, gy;
+            load_u<R, NE>(U, g.es, mu * g.V + n, u);
+            load_g<R>(gf, g.V, (1 - p) * g.Vh + pick4(fw.hb, mu), gy);
+            dm_mul(gx, u, gu);
+#pragma unroll
+            for (int e = 0; e < 9; e++) f += gu.re[e] * gy.re[e] + gu.im[e] * gy.im[e];
+        }
+    }
+    const double t = block_sum(f);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k_sum_partials(const double *__restrict__ part, int n, double *__restrict__ out) {
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+    const double t = block_sum(v);
+    if (threadIdx.x == 0) out[0] = t;
+}
+
+template <typename R, int NE>
+__global__ void k_functional_grad(Geom g, int nd, const typename V2<R>::type *__restrict__ U,
+                                  const R *__restrict__ s, const typename V2<R>::type *__restrict__ gf,
+                                  double scale, R *__restrict__ grad) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.V) return;
+    const int p = n >= g.Vh, h = n - p * g.Vh;
+    const SiteNbr fw = site_fwd_neighbours(g, p, h);
+    const SiteNbr bw = site_neighbours(g, p, h);
+    DMat K;
+#pragma unroll
+    for (int e = 0; e < 9; e++) { K.re[e] = 0.0; K.im[e] = 0.0; }
+    for (int mu = 0; mu < nd; mu++) {
+        DMat u, gy, t;
+        // U_mu(x) g(x+mu)^dagger
+        load_u<R, NE>(U, g.es, mu * g.V + n, u);
+        load_g<R>(gf, g.V, (1 - p) * g.Vh + pick4(fw.hb, mu), gy);
+        dm_mul_nd(u, gy, t);
+#pragma unroll
+        for (int e = 0; e < 9; e++) { K.re[e] += t.re[e]; K.im[e] += t.im[e]; }
+        // U_mu(x-mu)^dagger g(x-mu)^dagger
+        const int nb = (1 - p) * g.Vh + pick4(bw.hb, mu);
+        load_u<R, NE>(U, g.es, mu * g.V + nb, u);
+        load_g<R>(gf, g.V, nb, gy);
+        dm_mul_dd(u, gy, t);
+#pragma unroll
+        for (int e = 0; e < 9; e++) { K.re[e] += t.re[e]; K.im[e] += t.im[e]; }
+    }
+    double sv[8];
+    load_s(s, g.V, n, sv);
+    DMat S, gx, Y;
+    algebra_matrix(sv, S);
+    load_g<R>(gf, g.V, n, gx);
+    dm_mul(K, gx, Y);  // K e^S
+    // Psi = sum_k ad_S^k(Y) / (k+1)!
+    DMat Psi = Y, T = Y;
+    double ymax = 0.0;
+#pragma unroll
+    for (int e = 0; e < 9; e++) ymax = fmax(ymax, fabs(Y.re[e]) + fabs(Y.im[e]));
+    double fact = 1.0;
+    for (int k = 1; k <= 60; k++) {
+        DMat A, B;
+        dm_mul(S, T, A);
+        dm_mul(T, S, B);
+        double tmax = 0.0;
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            T.re[e] = A.re[e] - B.re[e];
+            T.im[e] = A.im[e] - B.im[e];
+            tmax = fmax(tmax, fabs(T.re[e]) + fabs(T.im[e]));
+        }
+        fact *= (k + 1);
+        const double inv = 1.0 / fact;
+#pragma unroll
+        for (int e = 0; e < 9; e++) { Psi.re[e] += T.re[e] * inv; Psi.im[e] += T.im[e] * inv; }
+        if (tmax * inv <= 1e-18 * ymax) break;
+    }
+    // Re Tr[(i lambda_a / 2) Psi] = -Im Tr[lambda_a Psi] / 2
+    const double r3 = 0.57735026918962576451;
+    double tr[8];
+    tr[0] = Psi.im[3] + Psi.im[1];                        // Im(P10 + P01)
+    tr[1] = -Psi.re[3] + Psi.re[1];                       // Im(-i P10 + i P01)
+    tr[2] = Psi.im[0] - Psi.im[4];
+    tr[3] = Psi.im[6] + Psi.im[2];
+    tr[4] = -Psi.re[6] + Psi.re[2];
+    tr[5] = Psi.im[7] + Psi.im[5];
+    tr[6] = -Psi.re[7] + Psi.re[5];
+    tr[7] = r3 * (Psi.im[0] + Psi.im[4] - 2.0 * Psi.im[8]);
+    const double c = scale / (2.0 * nd * 3.0 * (double)g.V);
+#pragma unroll
+    for (int a = 0; a < 8; a++) grad[(long long)a * g.V + n] = (R)(-tr[a] * c);
+}
+
+// U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger for all four mu.
+template <typename R, int NE>
+__global__ void k_gauge_transform(Geom g, typename V2<R>::type *__restrict__ U,
+                                  const typename V2<R>::type *__restrict__ gf) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= g.V) return;
+    const int p = n >= g.Vh, h = n - p * g.Vh;
+    const SiteNbr fw = site_fwd_neighbours(g, p, h);
+    DMat gx;
+    load_g<R>(gf, g.V, n, gx);
+    for (int mu = 0; mu < 4; mu++) {
+        DMat u, gy, t, r;
+        load_u<R, NE>(U, g.es, mu * g.V + n, u);
+        load_g<R>(gf, g.V, (1 - p) * g.Vh + pick4(fw.hb, mu), gy);
+        dm_mul(gx, u, t);
+        dm_mul_nd(t, gy, r);
+        Mat<R> m;
+#pragma unroll
+        for (int e = 0; e < 9; e++) { m.re[e] = (R)r.re[e]; m.im[e] = (R)r.im[e]; }
+        store_link<R, NE, false>(m, as_global((void *)U), g.es, mu * g.V + n);
+    }
+}
+
+constexpr int GB = 256;
+
+hipError_t launch_expS(int prec, const Geom &g, const void *s, void *gfield, hipStream_t st) {
+    const dim3 grid((g.V + GB - 1) / GB);
+    if (prec == 0)
+        hipLaunchKernelGGL(k_expS<double>, grid, dim3(GB), 0, st, g, (const double *)s,
+                           (V2<double>::type *)gfield);
+    else
+        hipLaunchKernelGGL(k_expS<float>, grid, dim3(GB), 0, st, g, (const float *)s,
+                           (V2<float>::type *)gfield);
+    return hipGetLastError();
+}
+
+hipError_t launch_functional(int prec, int nelem, int gauge, const Geom &g, const void *U,
+                             const void *gfield, double *d_partials, hipStream_t st) {
+    const dim3 grid((g.V + GB - 1) / GB);
+    const int nd = gauge == 0 ? 4 : 3;
+#define GF_L(R, NE)                                                                               \
+    hipLaunchKernelGGL((k_functional<R, NE>), grid, dim3(GB), 0, st, g, nd,                       \
+                       (const V2<R>::type *)U, (const V2<R>::type *)gfield, d_partials)
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else GF_L(double, 6); }
+    else { if (nelem == 9) GF_L(float, 9); else GF_L(float, 6); }
+#undef GF_L
+    return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const double *d_partials, int n, double *d_out, hipStream_t st) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, st, d_partials, n, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_functional_grad(int prec, int nelem, int gauge, const Geom &g, const void *U,
+                                  const void *s, const void *gfield, double scale, void *grad,
+                                  hipStream_t st) {
+    const dim3 grid((g.V + GB - 1) / GB);
+    const int nd = gauge == 0 ? 4 : 3;
+#define GF_L(R, NE)                                                                               \
+    hipLaunchKernelGGL((k_functional_grad<R, NE>), grid, dim3(GB), 0, st, g, nd,                  \
+                       (const V2<R>::type *)U, (const R *)s, (const V2<R>::type *)gfield, scale,   \
+                       (R *)grad)
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else GF_L(double, 6); }
+    else { if (nelem == 9) GF_L(float, 9); else GF_L(float, 6); }
+#undef GF_L
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge_transform(int prec, int nelem, const Geom &g, void *U, const void *gfield,
+                                  hipStream_t st) {
+    const dim3 grid((g.V + GB - 1) / GB);
+#define GF_L(R, NE)                                                                               \
+    hipLaunchKernelGGL((k_gauge_transform<R, NE>), grid, dim3(GB), 0, st, g, (V2<R>::type *)U,     \
+                       (const V2<R>::type *)gfield)
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else GF_L(double, 6); }
+    else { if (nelem == 9) GF_L(float, 9); else GF_L(float, 6); }
+#undef GF_L
+    return hipGetLastError();
+}
+
+}  // namespace gf

@@ -1,0 +1,150 @@
+// quality.hip -- F (eq. 1) and theta (eqs. 2-3) of every ensemble member,
+// reduced in double in a fixed order.
+//
+// Stage 1: one workgroup per tile of QTILE consecutive sites (site index
+// n = p*V/2 + h over both parities); each lane reads the eight links of its
+// site, forms Delta(x) = A - (Tr A / 3) 1 with A = M - M^dagger,
+// M = sum_nu [U_nu(x - nu) - U_nu(x)] and the site's Re Tr of its forward
+// links, all in double (float links are promoted exactly). The workgroup
+// sums its lanes with a fixed xor-butterfly and writes one partial pair.
+// Stage 2: one workgroup per member sums that member's partials, strided
+// per lane then by the same fixed butterfly, and normalises. Neither stage
+// depends on the sweep schedule, so F and theta are bitwise reproducible.
+#include "su3_device.hpp"
+
+namespace gf {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = v + __shfl_xor(v, m);
+    return v;
+}
+
+// Sum a pair over a workgroup of up to 1024 lanes (fixed order): result in
+// lane 0.
+__device__ __forceinline__ void block_sum2(double &a, double &b) {
+    __shared__ double sa[16], sb[16];
+    a = wave_sum(a);
+    b = wave_sum(b);
+    const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int nw = (blockDim.x + 63) / 64;
+    if (lane == 0) { sa[wid] = a; sb[wid] = b; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tb = 0.0;
+        for (int w = 0; w < nw; w++) { ta += sa[w]; tb += sb[w]; }
+        a = ta;
+        b = tb;
+    }
+}
+
+template <typename R, int NE>
+__global__ void __launch_bounds__(QTILE)
+k_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
+          const int *__restrict__ active, double *__restrict__ partials) {
+    const int tile = blockIdx.x;
+    const int c = qtile_cfg[tile];
+    if (active && !active[c]) return;
+    const CfgDesc d = desc[c];
+    const Geom &g = d.g;
+    const int n = (tile - d.qtile0) * QTILE + threadIdx.x;
+    const int nd = d.gauge == 0 ? 4 : 3;
+    double fsum = 0.0, tsum = 0.0;
+    if (n < g.V) {
+        const int p = n >= g.Vh;
+        const int h = n - p * g.Vh;
+        const SiteNbr nb = site_neighbours(g, p, h);
+        const gchar *U = as_global(d.U);
+        double mr[9], mi[9];
+#pragma unroll
+        for (int e = 0; e < 9; e++) { mr[e] = 0.0; mi[e] = 0.0; }
+        for (int mu = 0; mu < nd; mu++) {
+            Mat<R> f, b;
+            load_link<R, NE, false>(f, U, g.es, mu * g.V + p * g.Vh + h);
+            load_link<R, NE, false>(b, U, g.es, mu * g.V + (1 - p) * g.Vh + pick4(nb.hb, mu));
+            fsum += (double)f.re[0] + (double)f.re[4] + (double)f.re[8];
+#pragma unroll
+            for (int e = 0; e < 9; e++) {
+                mr[e] += (double)b.re[e] - (double)f.re[e];
+                mi[e] += (double)b.im[e] - (double)f.im[e];
+            }
+        }
+        // A = M - M^dagger: A_rc = M_rc - conj(M_cr)
+        double ar[9], ai[9];
+#pragma unroll
+        for (int r = 0; r < 3; r++)
+#pragma unroll
+            for (int cc = 0; cc < 3; cc++) {
+                ar[3 * r + cc] = mr[3 * r + cc] - mr[3 * cc + r];
+                ai[3 * r + cc] = mi[3 * r + cc] + mi[3 * cc + r];
+            }
+        const double trr = (ar[0] + ar[4] + ar[8]) / 3.0;
+        const double tri = (ai[0] + ai[4] + ai[8]) / 3.0;
+#pragma unroll
+        for (int r = 0; r < 3; r++) { ar[4 * r] -= trr; ai[4 * r] -= tri; }
+#pragma unroll
+        for (int e = 0; e < 9; e++) tsum += ar[e] * ar[e] + ai[e] * ai[e];
+    }
+    block_sum2(fsum, tsum);
+    if (threadIdx.x == 0) {
+        partials[2 * tile] = fsum;
+        partials[2 * tile + 1] = tsum;
+    }
+}
+
+// One workgroup per member. With update_active: members that were active
+// get iters += swept, and are retired once theta < eps; retired members
+// keep their previous result.
+__global__ void __launch_bounds__(256)
+k_quality_final(const CfgDesc *__restrict__ desc, const double *__restrict__ partials,
+                double *__restrict__ result, int *__restrict__ active, int *__restrict__ iters,
+                int swept, double eps, int update_active) {
+    const int c = blockIdx.x;
+    if (update_active && !active[c]) return;
+    const CfgDesc d = desc[c];
+    double fs = 0.0, ts = 0.0;
+    for (int t = threadIdx.x; t < d.nqtiles; t += blockDim.x) {
+        fs += partials[2 * (d.qtile0 + t)];
+        ts += partials[2 * (d.qtile0 + t) + 1];
+    }
+    block_sum2(fs, ts);
+    if (threadIdx.x == 0) {
+        const int nd = d.gauge == 0 ? 4 : 3;
+        const double F = fs / (nd * 3.0 * (double)d.g.V);
+        const double th = ts / (3.0 * (double)d.g.V);
+        result[2 * c] = F;
+        result[2 * c + 1] = th;
+        if (update_active) {
+            iters[c] += swept;
+            if (th < eps) active[c] = 0;
+        }
+    }
+}
+
+template <typename R, int NE>
+static hipError_t launch_q(const CfgDesc *d_desc, const int *d_qtile_cfg, const int *d_active,
+                           int nqtiles, double *d_partials, hipStream_t st) {
+    if (nqtiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_quality<R, NE>), dim3(nqtiles), dim3(QTILE), 0, st, d_desc, d_qtile_cfg,
+                       d_active, d_partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int *d_qtile_cfg,
+                          const int *d_active, int nqtiles, double *d_partials, hipStream_t st) {
+    if (prec == 0)
+        return nelem == 9 ? launch_q<double, 9>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st)
+                          : launch_q<double, 6>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st);
+    return nelem == 9 ? launch_q<float, 9>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st)
+                      : launch_q<float, 6>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st);
+}
+
+hipError_t launch_quality_final(const CfgDesc *d_desc, int n, const double *d_partials,
+                                double *d_result, int *d_active, int *d_iters, int swept,
+                                double eps, int update_active, hipStream_t st) {
+    hipLaunchKernelGGL(k_quality_final, dim3(n), dim3(256), 0, st, d_desc, d_partials, d_result,
+                       d_active, d_iters, swept, eps, update_active);
+    return hipGetLastError();
+}
+
+}  // namespace gf

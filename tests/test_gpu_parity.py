@@ -1,0 +1,264 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, called through the
+C ABI. Inputs are seeded synthetic fields; both sides get the same values
+(FP32 runs give the oracle the exact double promotion of the float field).
+
+Tolerances (derived from the arithmetic, not tuned):
+* FP64 links after a half-sweep: 1e-13 abs. Both sides do the same ~100
+  double operations per link; libm vs the kernel's own trig differ by an ulp.
+* FP32 links after a half-sweep: 5e-6 abs. The rotation is applied in float
+  (G rounded to float, ~6 products per entry: a few 6e-8 roundings, times the
+  3 subgroups).
+* F, theta: 1e-13 relative (F32 fields are promoted exactly, so only the
+  summation order differs).
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+LANDAU, COULOMB = 0, 1
+
+
+@pytest.fixture(scope="module")
+def gf():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1412_1498_amd import gf as mod
+    return mod
+
+
+def make_ctx(gf, dims, gauge, prec, **kw):
+    return gf.Context(dims, gauge=gauge, prec=prec, params=gf.default_params(prec, **kw))
+
+
+def to_gpu(ctx, U_np):
+    t = torch.from_numpy(np.ascontiguousarray(U_np)).to("cuda", dtype=ctx.cdtype)
+    return ctx.pack(t)
+
+
+def to_host(ctx, U):
+    return ctx.unpack(U).cpu().numpy().astype(np.complex128)
+
+
+def oracle_input(U_np, prec):
+    return U_np.astype(np.complex64).astype(np.complex128) if prec == 1 else U_np.copy()
+
+
+DIMS = [(4, 4, 4, 4), (4, 6, 2, 8), (6, 4, 4, 2), (8, 8, 8, 8)]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_pack_roundtrip(gf, field_cache, prec, storage):
+    dims = (4, 6, 2, 8)
+    U = field_cache(dims, 0.5, 1)
+    ctx = make_ctx(gf, dims, LANDAU, prec, storage=storage)
+    back = to_host(ctx, to_gpu(ctx, U))
+    src = oracle_input(U, prec)
+    if storage == 0:
+        np.testing.assert_array_equal(back, src)
+    else:
+        np.testing.assert_array_equal(back[..., :2, :], src[..., :2, :])
+        np.testing.assert_allclose(back[..., 2, :], src[..., 2, :], atol=1e-14 if prec == 0 else 2e-6)
+
+
+def test_internal_layout_positions(gf, field_cache):
+    """Element (r, c) of U_mu(x) sits at e*4V + mu*V + p*V/2 + (x + nx(y + ny(z + nz t)))/2."""
+    dims = (4, 2, 6, 2)
+    nx, ny, nz, nt = dims
+    U = field_cache(dims, 0.5, 2)
+    ctx = make_ctx(gf, dims, LANDAU, 0)
+    I = to_gpu(ctx, U).cpu().numpy()  # (9, 4, 2, V/2, 2)
+    for t in range(nt):
+        for z in range(nz):
+            for y in range(ny):
+                for x in range(nx):
+                    p = (x + y + z + t) & 1
+                    h = (x + nx * (y + ny * (z + nz * t))) // 2
+                    for mu in range(4):
+                        m = I[:, mu, p, h, 0] + 1j * I[:, mu, p, h, 1]
+                        np.testing.assert_array_equal(m.reshape(3, 3), U[t, z, y, x, mu])
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("dims", DIMS)
+def test_quality_matches_oracle(gf, oracle_lib, field_cache, prec, gauge, dims):
+    U = field_cache(dims, 0.7, 3)
+    ctx = make_ctx(gf, dims, gauge, prec)
+    F, th = ctx.quality(to_gpu(ctx, U))
+    Fo, tho = oracle_lib.quality(oracle_input(U, prec), dims, gauge)
+    assert abs(F - Fo) <= 1e-13 * abs(Fo)
+    assert abs(th - tho) <= 1e-13 * abs(tho)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("lps", [1, 2, 4, 8])
+@pytest.mark.parametrize("dims", DIMS[:3])
+def test_half_sweeps_match_oracle(gf, oracle_lib, field_cache, prec, gauge, lps, dims):
+    U = field_cache(dims, 0.7, 4)
+    ctx = make_ctx(gf, dims, gauge, prec, lanes_per_site=lps, block_threads=64)
+    Ug = to_gpu(ctx, U)
+    Uo = oracle_input(U, prec)
+    tol = 1e-13 if prec == 0 else 5e-6
+    for p in (0, 1, 0, 1):
+        ctx.sweep(Ug, p, 1.7)
+        oracle_lib.half_sweep(Uo, dims, p, 1.7, gauge)
+        err = np.abs(to_host(ctx, Ug) - Uo).max()
+        assert err < tol, (p, err)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_all_schedules_give_identical_bits(gf, field_cache, prec, storage):
+    dims = (8, 4, 6, 4)
+    U = field_cache(dims, 0.6, 5)
+    ref = None
+    for lps in (1, 2, 4, 8):
+        for block in (64, 128, 192, 256):
+            for nt in (0, 1):
+                ctx = make_ctx(gf, dims, LANDAU, prec, lanes_per_site=lps, block_threads=block,
+                               nontemporal=nt, storage=storage, reunit_every=2)
+                Ug = to_gpu(ctx, U)
+                ctx.sweeps(Ug, 1.7, 3)
+                out = Ug.cpu()
+                if ref is None:
+                    ref = out
+                else:
+                    assert torch.equal(out, ref), (lps, block, nt)
+
+
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+def test_fix_matches_oracle_fp64(gf, oracle_lib, field_cache, gauge):
+    """4^4, amp 0.3, seed 0, omega 1.7, theta < 1e-12 within 2000 sweeps."""
+    dims = (4, 4, 4, 4)
+    U = field_cache(dims, 0.3, 0)
+    ctx = make_ctx(gf, dims, gauge, 0, reunit_every=20)
+    Ug = to_gpu(ctx, U)
+    r = ctx.fix(Ug, 1.7, 1e-12, 2000)
+    Uo = U.copy()
+    ro = oracle_lib.fix(Uo, dims, 1.7, 1e-12, 2000, gauge, reunit_every=20)
+    assert r["converged"] and ro["converged"]
+    assert r["theta"] < 1e-12
+    assert abs(r["iters"] - ro["iters"]) <= 1
+    assert abs(r["F"] - ro["F"]) < 1e-12
+    if r["iters"] == ro["iters"]:
+        assert np.abs(to_host(ctx, Ug) - Uo).max() < 1e-11
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_fix_schedule_check_and_reunit(gf, oracle_lib, field_cache, prec):
+    """check_every = 5, reunit_every = 7, a max_iter that is not a multiple of
+    either: same sweeps, same final field as the oracle's Alg. 1."""
+    dims = (4, 6, 2, 8)
+    U = field_cache(dims, 0.5, 6)
+    ctx = make_ctx(gf, dims, LANDAU, prec, check_every=5, reunit_every=7)
+    Ug = to_gpu(ctx, U)
+    r = ctx.fix(Ug, 1.7, 0.0, 23)
+    Uo = oracle_input(U, prec)
+    ro = oracle_lib.fix(Uo, dims, 1.7, 0.0, 23, reunit_every=7, check_every=5)
+    assert r["iters"] == ro["iters"] == 23 and not r["converged"]
+    assert abs(r["F"] - ro["F"]) < (1e-13 if prec == 0 else 1e-6)
+    assert np.abs(to_host(ctx, Ug) - Uo).max() < (1e-12 if prec == 0 else 2e-5)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("storage", [0, 1])
+def test_reunit_matches_oracle(gf, oracle_lib, field_cache, prec, storage):
+    dims = (4, 4, 2, 2)
+    rng = np.random.default_rng(3)
+    U = field_cache(dims, 0.5, 7)
+    P = U + 1e-3 * (rng.standard_normal(U.shape) + 1j * rng.standard_normal(U.shape))
+    ctx = make_ctx(gf, dims, LANDAU, prec, storage=storage)
+    Ug = to_gpu(ctx, P)
+    ctx.reunit(Ug)
+    Po = oracle_input(P, prec)
+    if storage == 1:  # the device never sees the stored third row
+        Po = to_host(ctx, to_gpu(ctx, P))
+    oracle_lib.reunit(Po)
+    np.testing.assert_allclose(to_host(ctx, Ug), Po, atol=1e-14 if prec == 0 else 3e-7)
+
+
+@pytest.mark.parametrize("use_graph", [0, 1])
+def test_batch_fix_equals_single_fix(gf, field_cache, use_graph):
+    members = [((4, 4, 4, 4), LANDAU, 0.3, 10), ((6, 4, 4, 2), COULOMB, 0.4, 11),
+               ((8, 8, 8, 8), LANDAU, 0.5, 12), ((4, 6, 2, 8), LANDAU, 0.6, 13)]
+    prec = 1
+    kw = dict(check_every=4, reunit_every=10, use_graph=use_graph)
+    ens = gf.Context(None, prec=prec, params=gf.default_params(prec, **kw),
+                     ensemble=[(d, g) for d, g, _, _ in members])
+    Us = []
+    for d, g, amp, seed in members:
+        c1 = make_ctx(gf, d, g, prec)
+        Us.append(to_gpu(c1, field_cache(d, amp, seed)))
+    singles = [u.clone() for u in Us]
+    rb = ens.batch_fix(Us, 1.7, 1e-7, 3000)
+    assert rb["converged"]
+    for i, (d, g, _, _) in enumerate(members):
+        c1 = make_ctx(gf, d, g, prec, **kw)
+        r1 = c1.fix(singles[i], 1.7, 1e-7, 3000)
+        assert r1["iters"] == rb["iters"][i]
+        assert r1["F"] == rb["F"][i] and r1["theta"] == rb["theta"][i]
+        assert torch.equal(singles[i], Us[i])
+
+
+def test_fp32_reaches_target_and_tracks_fp64(gf, oracle_lib, field_cache):
+    dims = (8, 8, 8, 8)
+    U = field_cache(dims, 0.5, 14)
+    c32 = make_ctx(gf, dims, LANDAU, 1, check_every=10, reunit_every=10)
+    U32 = to_gpu(c32, U)
+    r32 = c32.fix(U32, 1.7, 1e-7, 5000)
+    Uo = U.copy()
+    ro = oracle_lib.fix(Uo, dims, 1.7, 1e-7, 5000, reunit_every=20, check_every=10)
+    assert r32["converged"] and r32["theta"] < 1e-7
+    assert abs(r32["F"] - ro["F"]) < 1e-5
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_timing_counts_half_sweeps(gf, field_cache, prec):
+    dims = (8, 8, 8, 8)
+    ctx = make_ctx(gf, dims, LANDAU, prec, timing=1)
+    Ug = to_gpu(ctx, field_cache(dims, 0.5, 15))
+    ctx.sweeps(Ug, 1.7, 5)
+    ms, n = ctx.timing()
+    assert n == 10 and ms > 0
+
+
+def test_full_size_48_fp32_sampled_sites(gf, oracle_lib):
+    """48^4, amp 0.7, FP32 links, the default schedule: after one even
+    half-sweep on the GPU, every sampled even site's eight links equal the
+    oracle's single-site update of the same (double-promoted) links; F does
+    not decrease; unitarity holds."""
+    from paper_1412_1498_amd import synth
+    dims = (48, 48, 48, 48)
+    U64 = synth.random_gauge_field(dims, 0.7, 0, device="cuda")
+    U32 = U64.to(torch.complex64)
+    del U64
+    ctx = make_ctx(gf, dims, LANDAU, 1)
+    Ug = ctx.pack(U32)
+    F0, _ = ctx.quality(Ug)
+    Uo = U32.cpu().numpy().astype(np.complex128)
+    del U32
+    ctx.sweep(Ug, 0, 1.7)
+    F1, _ = ctx.quality(Ug)
+    assert F1 >= F0
+    back = ctx.unpack(Ug).cpu().numpy()
+    rng = np.random.default_rng(0)
+    V = 48 ** 4
+    par = oracle_lib.parity_of_sites(dims)
+    sites = [s for s in rng.choice(V, 400, replace=False) if par[s] == 0][:128]
+    for s in sites:
+        oracle_lib.site_update(Uo, dims, int(s), 1.7)
+    Bo = Uo.reshape(V, 4, 3, 3)
+    Bg = back.reshape(V, 4, 3, 3)
+    nx = 48
+    for s in sites:
+        np.testing.assert_allclose(Bg[s], Bo[s], atol=5e-6)
+        x, y, z, t = s % nx, (s // nx) % nx, (s // nx ** 2) % nx, s // nx ** 3
+        for mu, step in enumerate([1, nx, nx ** 2, nx ** 3]):
+            c = [x, y, z, t][mu]
+            b = s - step if c > 0 else s + (nx - 1) * step
+            np.testing.assert_allclose(Bg[b, mu], Bo[b, mu], atol=5e-6)
+    L = Bg[sites].reshape(-1, 3, 3)
+    assert np.abs(L @ L.conj().transpose(0, 2, 1) - np.eye(3)).max() < 2e-6
