@@ -78,7 +78,7 @@ def main():
     ap.add_argument("--storage", type=int, choices=[18, 12], default=18)
     ap.add_argument("--lps", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
-    ap.add_argument("--nontemporal", type=int, default=0)
+    ap.add_argument("--nontemporal", type=int, default=-1)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")

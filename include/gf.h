@@ -79,9 +79,10 @@ typedef struct gf_params {
     long long start_sweep;  /* global index of the last sweep already done
                                (sets the reunitarisation phase on resume) */
     int storage;            /* GF_STORE_18 (default) or GF_STORE_12 */
-    int lanes_per_site;     /* 0 = default, else 1, 2, 4 or 8 lanes per site */
+    int lanes_per_site;     /* 0 = default (2), else 1, 2, 4 or 8 lanes per site */
     int block_threads;      /* 0 = default, else 64, 128, 192 or 256 */
-    int nontemporal;        /* 1 = streaming (non-temporal) link loads/stores */
+    int nontemporal;        /* 1 = streaming (non-temporal) link loads/stores,
+                               0 = plain, -1 = default for the precision */
     int use_graph;          /* 1 = replay each check period as a hipGraph */
     int timing;             /* 1 = time every half-sweep with hipEvents */
 } gf_params;

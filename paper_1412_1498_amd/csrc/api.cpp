@@ -123,11 +123,14 @@ int check_omega(gf_ctx *ctx, double omega) {
     return GF_OK;
 }
 
+// Defaults from the schedule sweep at 48^4 on MI355X: two lanes per site;
+// 256-thread workgroups for float links, 128 for double; non-temporal
+// access pays for double and for 12-real float storage.
 Schedule default_schedule(int prec, const gf_params &p) {
     Schedule s;
-    s.lps = p.lanes_per_site > 0 ? p.lanes_per_site : 4;
-    s.block = p.block_threads > 0 ? p.block_threads : 256;
-    s.nt = p.nontemporal ? 1 : 0;
+    s.lps = p.lanes_per_site > 0 ? p.lanes_per_site : 2;
+    s.block = p.block_threads > 0 ? p.block_threads : (prec == GF_F64 ? 128 : 256);
+    s.nt = p.nontemporal >= 0 ? p.nontemporal : ((prec == GF_F64 || p.storage == GF_STORE_12) ? 1 : 0);
     return s;
 }
 
@@ -350,6 +353,7 @@ void gf_params_default(gf_params *p, int prec) {
     p->reunit_every = prec == GF_F64 ? 20 : 10;
     p->start_sweep = 0;
     p->storage = GF_STORE_18;
+    p->nontemporal = -1;
 }
 
 int gf_create(gf_ctx **out, const int dims[4], int nc, int gauge, int prec, void *stream,

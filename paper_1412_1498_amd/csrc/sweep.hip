@@ -6,55 +6,139 @@
 // same-parity sites share none, so the sites are independent and each link
 // is read and written exactly once per half-sweep.
 //
-// Register form: a forward link is held as W = U_mu(x), a backward one as
-// W = U_mu(x - mu)^dagger. Then the staple of eq. (5) is K = sum W over the
-// functional's directions, and the update U_mu(x) <- G U_mu(x),
-// U_mu(x - mu) <- U_mu(x - mu) G^dagger is the same row rotation W <- G W
-// for all eight links.
+// Per site: K(x) = sum_mu [U_mu(x) + U_mu(x - mu)^dagger] (eq. 5, the field
+// already carrying every transformation so far) is built once, in double.
+// Applying a subgroup element G to the site's links (U_mu(x) <- G U_mu(x),
+// U_mu(x - mu) <- U_mu(x - mu) G^dagger) maps K to G K exactly, so the three
+// subgroup steps of Alg. 1 -- solve eq. (6) on the (a, b) block, over-relax,
+// rotate -- are carried out on K alone, in double, and the product
+// G3 G2 G1 is applied to each of the eight links once at the end. The result
+// is that of rotating the links after every subgroup, with two fewer
+// roundings of each link.
 //
-// Schedules: LPS lanes cooperate on one site (LPS = 1, 2, 4, 8), each lane
-// holding 8/LPS links. A lane forms the quaternion part of its links' (a, b)
-// blocks in double, sums them in the fixed tree
-//     ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7))
-// (slots 0-3 forward mu = 0..3, 4-7 backward), finishing the upper levels
-// with xor-shuffles between the site's lanes; every lane then solves the
-// SU(2) problem redundantly and rotates its own links. The tree is the same
-// for every LPS, so all schedules produce bitwise identical links. Links are
-// rotated in the link precision with explicit fma; the solve, the power
-// g^omega and reunitarisation run in double.
+// Schedules: LPS lanes cooperate on a site (LPS = 1, 2, 4, 8), each holding
+// 8/LPS links. Link slots are ordered (fwd 0, bwd 0, fwd 1, bwd 1, ...,
+// fwd 3, bwd 3); a lane owns consecutive slots and K is summed over slots in
+// the fixed tree ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)), the
+// upper levels by xor-shuffles between the site's lanes. Every lane then
+// runs the (cheap, double) subgroup steps redundantly. The tree does not
+// depend on LPS, so all schedules give bitwise identical links.
 #include "su3_device.hpp"
 
 namespace gf {
 
-struct Q4 { double v[4]; };
+// 3x3 complex matrix in double.
+struct DM {
+    double re[9], im[9];
+};
 
 // The SU(2) solve with over-relaxation, kept out of line: inlined, its
 // double-precision temporaries are scheduled across the link registers and
 // raise the kernel's VGPR count by about half. Arguments and result travel
 // in registers.
+struct Q4 { double v[4]; };
+
 __device__ __attribute__((noinline)) Q4 su2_step(Q4 b, double omega) {
     Q4 r;
     gf_su2_overrelax(b.v, omega, r.v);
     return r;
 }
 
-// Fixed-tree sum of the quaternion parts (times 2) of the (a, b) blocks of
-// the lane's links LO .. LO+N-1; links outside the functional add 0.
+// Contribution of link slot k to K: the link itself (forward) or its
+// hermitian conjugate (backward), promoted to double.
+template <typename R>
+__device__ __forceinline__ void k_term(const Mat<R> &u, bool bwd, bool in, DM &t) {
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const int e = 3 * r + c, et = 3 * c + r;
+            const double xr = bwd ? (double)u.re[et] : (double)u.re[e];
+            const double xi = bwd ? -(double)u.im[et] : (double)u.im[e];
+            t.re[e] = in ? xr : 0.0;
+            t.im[e] = in ? xi : 0.0;
+        }
+}
+
+// Fixed-tree sum of the K terms of the lane's slots LO .. LO+N-1.
 template <int LO, int N, typename R, int L>
-__device__ __forceinline__ Q4 tree_quat(const Mat<R> (&w)[L], const bool (&inK)[L], int a, int b) {
-    Q4 r;
+__device__ __forceinline__ DM k_tree(const Mat<R> (&w)[L], const bool (&bwd)[L], const bool (&in)[L]) {
+    DM r;
     if constexpr (N == 1) {
-        double t[4];
-        block_quat2(w[LO], a, b, t);
-#pragma unroll
-        for (int i = 0; i < 4; i++) r.v[i] = inK[LO] ? t[i] : 0.0;
+        k_term(w[LO], bwd[LO], in[LO], r);
     } else {
-        const Q4 x = tree_quat<LO, N / 2>(w, inK, a, b);
-        const Q4 y = tree_quat<LO + N / 2, N / 2>(w, inK, a, b);
+        const DM x = k_tree<LO, N / 2>(w, bwd, in);
+        const DM y = k_tree<LO + N / 2, N / 2>(w, bwd, in);
 #pragma unroll
-        for (int i = 0; i < 4; i++) r.v[i] = x.v[i] + y.v[i];
+        for (int e = 0; e < 9; e++) { r.re[e] = x.re[e] + y.re[e]; r.im[e] = x.im[e] + y.im[e]; }
     }
     return r;
+}
+
+// Rows a, b of m <- g (rows a, b of m); g = [[g0 + i g3, g2 + i g1],
+// [-g2 + i g1, g0 - i g3]] in double.
+__device__ __forceinline__ void rot_rows_d(DM &m, int a, int b, const Q4 &g) {
+    const double ar = g.v[0], ai = g.v[3], br = g.v[2], bi = g.v[1];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const double xr = m.re[3 * a + c], xi = m.im[3 * a + c];
+        const double yr = m.re[3 * b + c], yi = m.im[3 * b + c];
+        m.re[3 * a + c] = ar * xr - ai * xi + (br * yr - bi * yi);
+        m.im[3 * a + c] = ar * xi + ai * xr + (br * yi + bi * yr);
+        m.re[3 * b + c] = -br * xr - bi * xi + (ar * yr + ai * yi);
+        m.im[3 * b + c] = -br * xi + bi * xr + (ar * yi - ai * yr);
+    }
+}
+
+// u <- g u (forward link) or u <- u g^dagger (backward link), g in the
+// link precision.
+template <typename R>
+__device__ __forceinline__ void apply_left(Mat<R> &u, const Mat<R> &g) {
+    Mat<R> o;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            R sr = g.re[3 * r] * u.re[c];
+            R si = g.re[3 * r] * u.im[c];
+            sr = fma(-g.im[3 * r], u.im[c], sr);
+            si = fma(g.im[3 * r], u.re[c], si);
+#pragma unroll
+            for (int k = 1; k < 3; k++) {
+                sr = fma(g.re[3 * r + k], u.re[3 * k + c], sr);
+                sr = fma(-g.im[3 * r + k], u.im[3 * k + c], sr);
+                si = fma(g.re[3 * r + k], u.im[3 * k + c], si);
+                si = fma(g.im[3 * r + k], u.re[3 * k + c], si);
+            }
+            o.re[3 * r + c] = sr;
+            o.im[3 * r + c] = si;
+        }
+    u = o;
+}
+
+template <typename R>
+__device__ __forceinline__ void apply_right_dag(Mat<R> &u, const Mat<R> &g) {
+    // (u g^dagger)_rc = sum_k u_rk conj(g_ck)
+    Mat<R> o;
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            R sr = u.re[3 * r] * g.re[3 * c];
+            R si = u.im[3 * r] * g.re[3 * c];
+            sr = fma(u.im[3 * r], g.im[3 * c], sr);
+            si = fma(-u.re[3 * r], g.im[3 * c], si);
+#pragma unroll
+            for (int k = 1; k < 3; k++) {
+                sr = fma(u.re[3 * r + k], g.re[3 * c + k], sr);
+                sr = fma(u.im[3 * r + k], g.im[3 * c + k], sr);
+                si = fma(u.im[3 * r + k], g.re[3 * c + k], si);
+                si = fma(-u.re[3 * r + k], g.im[3 * c + k], si);
+            }
+            o.re[3 * r + c] = sr;
+            o.im[3 * r + c] = si;
+        }
+    u = o;
 }
 
 template <typename R, int NE, int LPS, bool NT>
@@ -66,47 +150,75 @@ __device__ __forceinline__ void or_site(const CfgDesc &d, int p, int h, int sub,
     const bool landau = d.gauge == 0;
 
     int off[L];
-    bool fwd[L];
-    bool inK[L];
+    bool bwd[L], in[L];
 #pragma unroll
     for (int k = 0; k < L; k++) {
         const int slot = sub * L + k;
-        const int mu = slot & 3;
-        const bool f = slot < 4;
-        const int hh = f ? h : pick4(nb.hb, mu);
-        off[k] = mu * g.V + (f ? p : 1 - p) * g.Vh + hh;
-        fwd[k] = f;
-        inK[k] = landau || mu != 3;
+        const int mu = slot >> 1;
+        const bool b = (slot & 1) != 0;  // compile-time unless LPS == 8
+        off[k] = mu * g.V + (b ? (1 - p) * g.Vh + pick4(nb.hb, mu) : p * g.Vh + h);
+        bwd[k] = b;
+        in[k] = landau || mu != 3;
     }
 
     Mat<R> w[L];
 #pragma unroll
-    for (int k = 0; k < L; k++) {
-        load_link<R, NE, NT>(w[k], U, g.es, off[k]);
-        dagger_if(w[k], !fwd[k]);
+    for (int k = 0; k < L; k++) load_link<R, NE, NT>(w[k], U, g.es, off[k]);
+
+    // K, summed in the fixed tree
+    DM K = k_tree<0, L>(w, bwd, in);
+#pragma unroll
+    for (int m = 1; m < LPS; m <<= 1) {
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            K.re[e] = K.re[e] + __shfl_xor(K.re[e], m);
+            K.im[e] = K.im[e] + __shfl_xor(K.im[e], m);
+        }
     }
 
+    // three subgroup steps on K: (0,1), (0,2), (1,2)
+    Q4 gs[3];
 #pragma unroll
     for (int sg = 0; sg < 3; sg++) {
-        const int a = sg == 2 ? 1 : 0, b = sg == 0 ? 1 : 2;  // (0,1), (0,2), (1,2)
-        const Q4 tq = tree_quat<0, L>(w, inK, a, b);
-        double q[4];
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            double v = tq.v[i];
-#pragma unroll
-            for (int m = 1; m < LPS; m <<= 1) v = v + __shfl_xor(v, m);
-            q[i] = 0.5 * v;
-        }
-        const Q4 r = su2_step(Q4{{q[0], q[1], q[2], q[3]}}, d.omega);
-        const R gq[4] = {(R)r.v[0], (R)r.v[1], (R)r.v[2], (R)r.v[3]};
-#pragma unroll
-        for (int k = 0; k < L; k++) rotate_rows(w[k], a, b, gq);
+        const int a = sg == 2 ? 1 : 0, b = sg == 0 ? 1 : 2;
+        const int aa = 4 * a, bb = 4 * b, ab = 3 * a + b, ba = 3 * b + a;
+        Q4 q;
+        q.v[0] = 0.5 * (K.re[aa] + K.re[bb]);
+        q.v[1] = 0.5 * (K.im[ab] + K.im[ba]);
+        q.v[2] = 0.5 * (K.re[ab] - K.re[ba]);
+        q.v[3] = 0.5 * (K.im[aa] - K.im[bb]);
+        gs[sg] = su2_step(q, d.omega);
+        if (sg < 2) rot_rows_d(K, a, b, gs[sg]);
     }
+
+    // G = G3 G2 G1 (double), rounded to the link precision
+    DM T;
+#pragma unroll
+    for (int e = 0; e < 9; e++) { T.re[e] = (e % 4 == 0) ? 1.0 : 0.0; T.im[e] = 0.0; }
+    rot_rows_d(T, 0, 1, gs[0]);
+    rot_rows_d(T, 0, 2, gs[1]);
+    rot_rows_d(T, 1, 2, gs[2]);
+    Mat<R> G;
+#pragma unroll
+    for (int e = 0; e < 9; e++) { G.re[e] = (R)T.re[e]; G.im[e] = (R)T.im[e]; }
 
 #pragma unroll
     for (int k = 0; k < L; k++) {
-        dagger_if(w[k], !fwd[k]);
+        if (LPS == 8) {
+            // the lane's one link is forward or backward at run time
+            Mat<R> f = w[k], r = w[k];
+            apply_left(f, G);
+            apply_right_dag(r, G);
+#pragma unroll
+            for (int e = 0; e < 9; e++) {
+                w[k].re[e] = bwd[k] ? r.re[e] : f.re[e];
+                w[k].im[e] = bwd[k] ? r.im[e] : f.im[e];
+            }
+        } else if (bwd[k]) {
+            apply_right_dag(w[k], G);
+        } else {
+            apply_left(w[k], G);
+        }
         if (reunit) reunitarise(w[k]);
         store_link<R, NE, NT>(w[k], U, g.es, off[k]);
     }
@@ -116,8 +228,16 @@ __device__ __forceinline__ void or_site(const CfgDesc &d, int p, int h, int sub,
 // grid-stride form was measured to double the register footprint, since
 // loop-invariant state stays live across the tile loop, so every tile gets
 // its own workgroup; the dispatcher balances the tiles over the CUs.)
+// Occupancy target: the float kernel with two lanes per site fits 2 waves per
+// SIMD (<= 256 VGPRs) without spilling only when asked to; the other
+// schedules settle at their natural register counts.
+template <typename R, int LPS> struct Waves {
+    static constexpr int lo = (sizeof(R) == 4 && LPS == 2) ? 2 : 1;
+    static constexpr int hi = (sizeof(R) == 4 && LPS == 2) ? 2 : 8;
+};
+
 template <typename R, int NE, int LPS, bool NT>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Waves<R, LPS>::lo, Waves<R, LPS>::hi)))
 k_half_sweep(const CfgDesc *__restrict__ desc, const int *__restrict__ tile_cfg,
              const int *__restrict__ active, int parity, int reunit) {
     const int tile = blockIdx.x;
