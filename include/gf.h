@@ -29,13 +29,17 @@
  * - Field pointers (U) are caller-owned DEVICE pointers, at least 256-byte
  *   aligned (a torch tensor's data_ptr()), in the internal layout below. The
  *   library never allocates, frees or keeps them beyond a call.
- * - Internal link layout (section "Implementation" of the paper): even and
- *   odd sites are stored separately and each matrix element has its own
- *   array. The complex element (row r, col c), e = 3r + c, of U_mu(x) sits at
- *       e * 4V + mu * V + p * V/2 + h,   h = (x + nx(y + ny(z + nz t))) / 2
- *   in units of one complex (float2 for F32, double2 for F64). With 12-real
- *   storage (gf_params.storage = GF_STORE_12) only e = 0..5 (rows 0 and 1)
- *   are stored and row 2 is rebuilt as conj(row0 x row1).
+ * - Internal link layout. As in the paper's implementation section, sites
+ *   are split by parity p = (x + y + z + t) mod 2 and numbered within a
+ *   parity by h = (x + nx(y + ny(z + nz t))) / 2. The sites of one parity are
+ *   grouped in blocks of 64 consecutive h; a block holds, for mu = 0..3 and
+ *   each stored complex element e = 3 row + col, the 64 values of that element
+ *   contiguously. The complex element e of U_mu at site (p, h) sits at
+ *       (((p * nb + h / 64) * 4 + mu) * ne + e) * 64 + h % 64
+ *   (units of one complex: float2 for F32, double2 for F64), with
+ *   nb = ceil(V / 128) blocks per parity and ne = 9 (18-real storage) or 6
+ *   (12-real storage, gf_params.storage = GF_STORE_12: rows 0 and 1 only, row
+ *   2 rebuilt as conj(row0 x row1)). The last block of a parity is padded.
  * - Canonical layout (pack/unpack only): [t][z][y][x][mu][row][col] complex
  *   in the context's precision.
  * - All work is enqueued on the context's HIP stream (the stream handle passed
@@ -79,7 +83,7 @@ typedef struct gf_params {
     long long start_sweep;  /* global index of the last sweep already done
                                (sets the reunitarisation phase on resume) */
     int storage;            /* GF_STORE_18 (default) or GF_STORE_12 */
-    int lanes_per_site;     /* 0 = default (2), else 1, 2, 4 or 8 lanes per site */
+    int lanes_per_site;     /* 0 = default (1), else 1, 2, 4 or 8 lanes per site */
     int block_threads;      /* 0 = default, else 64, 128, 192 or 256 */
     int nontemporal;        /* 1 = streaming (non-temporal) link loads/stores,
                                0 = plain, -1 = default for the precision */
@@ -113,7 +117,7 @@ int gf_destroy(gf_ctx *ctx);
 const char *gf_last_error(const gf_ctx *ctx);
 
 /* Bytes of one field of member i in the internal layout:
- * nelem * 4V * sizeof(complex), nelem = 9 (18-real) or 6 (12-real). */
+ * 2 * nb * 4 * ne * 64 * sizeof(complex) (padding included). */
 size_t gf_field_bytes(const gf_ctx *ctx, int member);
 
 /* Convert member 0's field between the canonical layout U_aos (device) and
@@ -214,9 +218,10 @@ void gf_host_su2_step(const double b[4], double omega, double r[4]);
  * and arctangent: out = {sin x, cos x, atan2(y, x)}. */
 void gf_host_trig(double x, double y, double out[3]);
 
-/* Index check: complex-element offsets (element e = 0) of the eight links that the site
- * (parity, h) of a dims lattice updates in a half-sweep: out[0..3] =
- * U_mu(x), out[4..7] = U_mu(x - mu). Returns GF_EINVAL for bad arguments. */
+/* Index check: complex offsets of element 0 of the eight links (18-real
+ * storage) that the site (parity, h) of a dims lattice updates in a
+ * half-sweep: out[0..3] = U_mu(x), out[4..7] = U_mu(x - mu). Returns
+ * GF_EINVAL for bad arguments. */
 int gf_site_links(const int dims[4], int parity, long long h, long long out[8]);
 
 #ifdef __cplusplus

@@ -123,14 +123,15 @@ int check_omega(gf_ctx *ctx, double omega) {
     return GF_OK;
 }
 
-// Defaults from the schedule sweep at 48^4 on MI355X: two lanes per site;
-// 256-thread workgroups for float links, 128 for double; non-temporal
-// access pays for double and for 12-real float storage.
+// Defaults from the schedule sweep at 48^4 on MI355X (blocked layout): one
+// lane per site with non-temporal link traffic; 128-thread workgroups, 256
+// for 12-real float storage.
 Schedule default_schedule(int prec, const gf_params &p) {
     Schedule s;
-    s.lps = p.lanes_per_site > 0 ? p.lanes_per_site : 2;
-    s.block = p.block_threads > 0 ? p.block_threads : (prec == GF_F64 ? 128 : 256);
-    s.nt = p.nontemporal >= 0 ? p.nontemporal : ((prec == GF_F64 || p.storage == GF_STORE_12) ? 1 : 0);
+    s.lps = p.lanes_per_site > 0 ? p.lanes_per_site : 1;
+    s.block = p.block_threads > 0 ? p.block_threads
+                                   : ((prec == GF_F32 && p.storage == GF_STORE_12) ? 256 : 128);
+    s.nt = p.nontemporal >= 0 ? p.nontemporal : 1;
     return s;
 }
 
@@ -278,12 +279,6 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
     if (p.storage != GF_STORE_18 && p.storage != GF_STORE_12) return GF_EINVAL;
     Schedule s = default_schedule(prec, p);
     if (check_schedule(&tmp, s) != GF_OK) return GF_EINVAL;
-    // kernels address an element array with 32-bit byte offsets
-    const long long csz = prec == GF_F64 ? 16 : 8;
-    for (int c = 0; c < n; c++) {
-        const int *d = dims + 4 * c;
-        if (4LL * d[0] * d[1] * d[2] * d[3] * csz >= (1LL << 32)) return GF_EINVAL;
-    }
 
     gf_ctx *ctx = new gf_ctx();
     ctx->n = n;
@@ -301,7 +296,7 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
     for (int c = 0; c < n; c++) {
         CfgDesc &d = ctx->desc[c];
         std::memset(&d, 0, sizeof d);
-        d.g = make_geom(dims + 4 * c);
+        d.g = make_geom(dims + 4 * c, ctx->nelem);
         d.gauge = gauge[c];
         d.omega = 1.0;
         d.qtile0 = nq;
@@ -403,7 +398,7 @@ const char *gf_last_error(const gf_ctx *ctx) { return ctx ? ctx->err.c_str() : "
 
 size_t gf_field_bytes(const gf_ctx *ctx, int member) {
     if (!ctx || member < 0 || member >= ctx->n) return 0;
-    return (size_t)ctx->nelem * (size_t)ctx->desc[member].g.es * csize(ctx);
+    return (size_t)field_complex(ctx->desc[member].g) * csize(ctx);
 }
 
 int gf_pack(gf_ctx *ctx, const void *U_aos, void *U) {
@@ -803,12 +798,12 @@ void gf_host_trig(double x, double y, double out[3]) {
 int gf_site_links(const int dims[4], int parity, long long h, long long out[8]) {
     gf_ctx tmp;
     if (!out || check_dims(&tmp, dims) != GF_OK || (parity != 0 && parity != 1)) return GF_EINVAL;
-    const Geom g = make_geom(dims);
+    const Geom g = make_geom(dims, 9);
     if (h < 0 || h >= g.Vh) return GF_EINVAL;
     const SiteNbr nb = site_neighbours(g, parity, (int)h);
     for (int mu = 0; mu < 4; mu++) {
-        out[mu] = (long long)mu * g.V + (long long)parity * g.Vh + h;
-        out[4 + mu] = (long long)mu * g.V + (long long)(1 - parity) * g.Vh + nb.hb[mu];
+        out[mu] = link_off(g, mu, parity, (int)h);
+        out[4 + mu] = link_off(g, mu, 1 - parity, nb.hb[mu]);
     }
     return GF_OK;
 }

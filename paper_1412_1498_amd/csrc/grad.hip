@@ -135,9 +135,9 @@ __device__ __forceinline__ void load_g(const typename V2<R>::type *__restrict__ 
 }
 
 template <typename R, int NE>
-__device__ __forceinline__ void load_u(const typename V2<R>::type *__restrict__ U, long long es, int off, DMat &m) {
+__device__ __forceinline__ void load_u(const typename V2<R>::type *__restrict__ U, long long off, DMat &m) {
     Mat<R> t;
-    load_link<R, NE, false>(t, as_global((const void *)U), es, off);
+    load_link<R, NE, false>(t, as_global((const void *)U), off);
 #pragma unroll
     for (int e = 0; e < 9; e++) { m.re[e] = t.re[e]; m.im[e] = t.im[e]; }
 }
@@ -187,7 +187,7 @@ __global__ void k_functional(Geom g, int nd, const typename V2<R>::type *__restr
         load_g<R>(gf, g.V, n, gx);
         for (int mu = 0; mu < nd; mu++) {
             DMat u, gu, gy;
-            load_u<R, NE>(U, g.es, mu * g.V + n, u);
+            load_u<R, NE>(U, link_off(g, mu, p, h), u);
             load_g<R>(gf, g.V, (1 - p) * g.Vh + pick4(fw.hb, mu), gy);
             dm_mul(gx, u, gu);
 #pragma unroll
@@ -220,14 +220,14 @@ __global__ void k_functional_grad(Geom g, int nd, const typename V2<R>::type *__
     for (int mu = 0; mu < nd; mu++) {
         DMat u, gy, t;
         // U_mu(x) g(x+mu)^dagger
-        load_u<R, NE>(U, g.es, mu * g.V + n, u);
+        load_u<R, NE>(U, link_off(g, mu, p, h), u);
         load_g<R>(gf, g.V, (1 - p) * g.Vh + pick4(fw.hb, mu), gy);
         dm_mul_nd(u, gy, t);
 #pragma unroll
         for (int e = 0; e < 9; e++) { K.re[e] += t.re[e]; K.im[e] += t.im[e]; }
         // U_mu(x-mu)^dagger g(x-mu)^dagger
         const int nb = (1 - p) * g.Vh + pick4(bw.hb, mu);
-        load_u<R, NE>(U, g.es, mu * g.V + nb, u);
+        load_u<R, NE>(U, link_off(g, mu, 1 - p, pick4(bw.hb, mu)), u);
         load_g<R>(gf, g.V, nb, gy);
         dm_mul_dd(u, gy, t);
 #pragma unroll
@@ -290,14 +290,14 @@ __global__ void k_gauge_transform(Geom g, typename V2<R>::type *__restrict__ U,
     load_g<R>(gf, g.V, n, gx);
     for (int mu = 0; mu < 4; mu++) {
         DMat u, gy, t, r;
-        load_u<R, NE>(U, g.es, mu * g.V + n, u);
+        load_u<R, NE>(U, link_off(g, mu, p, h), u);
         load_g<R>(gf, g.V, (1 - p) * g.Vh + pick4(fw.hb, mu), gy);
         dm_mul(gx, u, t);
         dm_mul_nd(t, gy, r);
         Mat<R> m;
 #pragma unroll
         for (int e = 0; e < 9; e++) { m.re[e] = (R)r.re[e]; m.im[e] = (R)r.im[e]; }
-        store_link<R, NE, false>(m, as_global((void *)U), g.es, mu * g.V + n);
+        store_link<R, NE, false>(m, as_global((void *)U), link_off(g, mu, p, h));
     }
 }
 

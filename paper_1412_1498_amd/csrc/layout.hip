@@ -19,15 +19,15 @@ __global__ void k_pack(Geom g, const typename V2<R>::type *__restrict__ aos,
     const int t = s / (g.nx * g.ny * g.nz);
     int p, h;
     site_to_ph(g, x, y, z, t, p, h);
-    const int off = mu * g.V + p * g.Vh + h;
+    const long long off = link_off(g, mu, p, h);
     const typename V2<R>::type *src = aos + idx * 9;
     typename V2<R>::type *dst = const_cast<typename V2<R>::type *>(aos) + idx * 9;
     if (!unpack) {
 #pragma unroll
-        for (int e = 0; e < NE; e++) U[e * g.es + off] = src[e];
+        for (int e = 0; e < NE; e++) U[off + (long long)e * BLK] = src[e];
     } else {
         Mat<R> m;
-        load_link<R, NE, false>(m, as_global((const void *)U), g.es, off);
+        load_link<R, NE, false>(m, as_global((const void *)U), off);
 #pragma unroll
         for (int e = 0; e < 9; e++) {
             typename V2<R>::type v;
@@ -38,14 +38,19 @@ __global__ void k_pack(Geom g, const typename V2<R>::type *__restrict__ aos,
     }
 }
 
+// One lane per (mu, site) link.
 template <typename R, int NE>
 __global__ void k_reunit(Geom g, typename V2<R>::type *__restrict__ U) {
     const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= 4LL * g.V) return;
+    const int mu = (int)(l / g.V);
+    const int n = (int)(l - (long long)mu * g.V);
+    const int p = n >= g.Vh, h = n - p * g.Vh;
+    const long long off = link_off(g, mu, p, h);
     Mat<R> m;
-    load_link<R, NE, false>(m, as_global((const void *)U), g.es, (int)l);
+    load_link<R, NE, false>(m, as_global((const void *)U), off);
     reunitarise(m);
-    store_link<R, NE, false>(m, as_global((void *)U), g.es, (int)l);
+    store_link<R, NE, false>(m, as_global((void *)U), off);
 }
 
 // One lane per site: canonical s[site][a] <-> internal s[a][p][h].

@@ -60,8 +60,8 @@ k_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
         for (int e = 0; e < 9; e++) { mr[e] = 0.0; mi[e] = 0.0; }
         for (int mu = 0; mu < nd; mu++) {
             Mat<R> f, b;
-            load_link<R, NE, false>(f, U, g.es, mu * g.V + p * g.Vh + h);
-            load_link<R, NE, false>(b, U, g.es, mu * g.V + (1 - p) * g.Vh + pick4(nb.hb, mu));
+            load_link<R, NE, false>(f, U, link_off(g, mu, p, h));
+            load_link<R, NE, false>(b, U, link_off(g, mu, 1 - p, pick4(nb.hb, mu)));
             fsum += (double)f.re[0] + (double)f.re[4] + (double)f.re[8];
 #pragma unroll
             for (int e = 0; e < 9; e++) {

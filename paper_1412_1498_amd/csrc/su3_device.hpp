@@ -62,15 +62,15 @@ __device__ __forceinline__ void rebuild_row2(Mat<R> &m) {
     }
 }
 
-// Link with complex index `off` inside each element array; element e starts
-// at base + e * es complex. NE = 9: full matrix; NE = 6: rows 0, 1 stored.
+// Link whose element 0 sits at complex offset `off` (see link_off); element
+// e is BLK complex values further. NE = 9: full matrix; NE = 6: rows 0, 1.
 template <typename R, int NE, bool NT>
-__device__ __forceinline__ void load_link(Mat<R> &m, const gchar *base, long long es, int off) {
+__device__ __forceinline__ void load_link(Mat<R> &m, const gchar *base, long long off) {
     typedef typename V2<R>::type v2;
-    const uint32_t bo = (uint32_t)off * (uint32_t)sizeof(v2);
+    const gchar *p = base + off * (long long)sizeof(v2);
 #pragma unroll
     for (int e = 0; e < NE; e++) {
-        v2 v = ld<NT, v2>(base + e * es * (long long)sizeof(v2), bo);
+        v2 v = ld<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)));
         m.re[e] = v.x;
         m.im[e] = v.y;
     }
@@ -78,15 +78,15 @@ __device__ __forceinline__ void load_link(Mat<R> &m, const gchar *base, long lon
 }
 
 template <typename R, int NE, bool NT>
-__device__ __forceinline__ void store_link(const Mat<R> &m, gchar *base, long long es, int off) {
+__device__ __forceinline__ void store_link(const Mat<R> &m, gchar *base, long long off) {
     typedef typename V2<R>::type v2;
-    const uint32_t bo = (uint32_t)off * (uint32_t)sizeof(v2);
+    gchar *p = base + off * (long long)sizeof(v2);
 #pragma unroll
     for (int e = 0; e < NE; e++) {
         v2 v;
         v.x = m.re[e];
         v.y = m.im[e];
-        st<NT, v2>(base + e * es * (long long)sizeof(v2), bo, v);
+        st<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)), v);
     }
 }
 

@@ -44,37 +44,6 @@ __device__ __attribute__((noinline)) Q4 su2_step(Q4 b, double omega) {
     return r;
 }
 
-// Contribution of link slot k to K: the link itself (forward) or its
-// hermitian conjugate (backward), promoted to double.
-template <typename R>
-__device__ __forceinline__ void k_term(const Mat<R> &u, bool bwd, bool in, DM &t) {
-#pragma unroll
-    for (int r = 0; r < 3; r++)
-#pragma unroll
-        for (int c = 0; c < 3; c++) {
-            const int e = 3 * r + c, et = 3 * c + r;
-            const double xr = bwd ? (double)u.re[et] : (double)u.re[e];
-            const double xi = bwd ? -(double)u.im[et] : (double)u.im[e];
-            t.re[e] = in ? xr : 0.0;
-            t.im[e] = in ? xi : 0.0;
-        }
-}
-
-// Fixed-tree sum of the K terms of the lane's slots LO .. LO+N-1.
-template <int LO, int N, typename R, int L>
-__device__ __forceinline__ DM k_tree(const Mat<R> (&w)[L], const bool (&bwd)[L], const bool (&in)[L]) {
-    DM r;
-    if constexpr (N == 1) {
-        k_term(w[LO], bwd[LO], in[LO], r);
-    } else {
-        const DM x = k_tree<LO, N / 2>(w, bwd, in);
-        const DM y = k_tree<LO + N / 2, N / 2>(w, bwd, in);
-#pragma unroll
-        for (int e = 0; e < 9; e++) { r.re[e] = x.re[e] + y.re[e]; r.im[e] = x.im[e] + y.im[e]; }
-    }
-    return r;
-}
-
 // Rows a, b of m <- g (rows a, b of m); g = [[g0 + i g3, g2 + i g1],
 // [-g2 + i g1, g0 - i g3]] in double.
 __device__ __forceinline__ void rot_rows_d(DM &m, int a, int b, const Q4 &g) {
@@ -90,11 +59,11 @@ __device__ __forceinline__ void rot_rows_d(DM &m, int a, int b, const Q4 &g) {
     }
 }
 
-// u <- g u (forward link) or u <- u g^dagger (backward link), g in the
-// link precision.
+// o = g u (forward link) or o = u g^dagger (backward link), g in the link
+// precision. The result goes to a separate matrix that is stored directly:
+// copying it back into u would make the compiler keep a private array.
 template <typename R>
-__device__ __forceinline__ void apply_left(Mat<R> &u, const Mat<R> &g) {
-    Mat<R> o;
+__device__ __forceinline__ void apply_left(const Mat<R> &u, const Mat<R> &g, Mat<R> &o) {
 #pragma unroll
     for (int r = 0; r < 3; r++)
 #pragma unroll
@@ -113,13 +82,11 @@ __device__ __forceinline__ void apply_left(Mat<R> &u, const Mat<R> &g) {
             o.re[3 * r + c] = sr;
             o.im[3 * r + c] = si;
         }
-    u = o;
 }
 
+// (u g^dagger)_rc = sum_k u_rk conj(g_ck)
 template <typename R>
-__device__ __forceinline__ void apply_right_dag(Mat<R> &u, const Mat<R> &g) {
-    // (u g^dagger)_rc = sum_k u_rk conj(g_ck)
-    Mat<R> o;
+__device__ __forceinline__ void apply_right_dag(const Mat<R> &u, const Mat<R> &g, Mat<R> &o) {
 #pragma unroll
     for (int r = 0; r < 3; r++)
 #pragma unroll
@@ -138,41 +105,63 @@ __device__ __forceinline__ void apply_right_dag(Mat<R> &u, const Mat<R> &g) {
             o.re[3 * r + c] = sr;
             o.im[3 * r + c] = si;
         }
-    u = o;
 }
 
-template <typename R, int NE, int LPS, bool NT>
-__device__ __forceinline__ void or_site(const CfgDesc &d, int p, int h, int sub, int reunit) {
+template <typename R, int NE, int LPS, bool NT, bool RU>
+__device__ __forceinline__ void or_site(const CfgDesc &d, int p, int h, int sub) {
     constexpr int L = 8 / LPS;  // links per lane
     const Geom &g = d.g;
     gchar *U = as_global(d.U);
     const SiteNbr nb = site_neighbours(g, p, h);
     const bool landau = d.gauge == 0;
 
-    int off[L];
+    long long off[L];
     bool bwd[L], in[L];
 #pragma unroll
     for (int k = 0; k < L; k++) {
         const int slot = sub * L + k;
         const int mu = slot >> 1;
         const bool b = (slot & 1) != 0;  // compile-time unless LPS == 8
-        off[k] = mu * g.V + (b ? (1 - p) * g.Vh + pick4(nb.hb, mu) : p * g.Vh + h);
+        off[k] = b ? link_off(g, mu, 1 - p, pick4(nb.hb, mu)) : link_off(g, mu, p, h);
         bwd[k] = b;
         in[k] = landau || mu != 3;
     }
 
     Mat<R> w[L];
 #pragma unroll
-    for (int k = 0; k < L; k++) load_link<R, NE, NT>(w[k], U, g.es, off[k]);
+    for (int k = 0; k < L; k++) load_link<R, NE, NT>(w[k], U, off[k]);
 
-    // K, summed in the fixed tree
-    DM K = k_tree<0, L>(w, bwd, in);
+    // K = sum over slots of U (forward) or U^dagger (backward), promoted to
+    // double; per element, the lane's slots are summed in place in the fixed
+    // tree, then the site's lanes combine by xor-shuffles.
+    DM K;
 #pragma unroll
-    for (int m = 1; m < LPS; m <<= 1) {
+    for (int r = 0; r < 3; r++) {
 #pragma unroll
-        for (int e = 0; e < 9; e++) {
-            K.re[e] = K.re[e] + __shfl_xor(K.re[e], m);
-            K.im[e] = K.im[e] + __shfl_xor(K.im[e], m);
+        for (int c = 0; c < 3; c++) {
+            const int e = 3 * r + c, et = 3 * c + r;
+            double tr[L], ti[L];
+#pragma unroll
+            for (int k = 0; k < L; k++) {
+                const double xr = bwd[k] ? (double)w[k].re[et] : (double)w[k].re[e];
+                const double xi = bwd[k] ? -(double)w[k].im[et] : (double)w[k].im[e];
+                tr[k] = in[k] ? xr : 0.0;
+                ti[k] = in[k] ? xi : 0.0;
+            }
+#pragma unroll
+            for (int step = 1; step < L; step *= 2)
+#pragma unroll
+                for (int k = 0; k < L; k += 2 * step) {
+                    tr[k] = tr[k] + tr[k + step];
+                    ti[k] = ti[k] + ti[k + step];
+                }
+#pragma unroll
+            for (int m = 1; m < LPS; m <<= 1) {
+                tr[0] = tr[0] + __shfl_xor(tr[0], m);
+                ti[0] = ti[0] + __shfl_xor(ti[0], m);
+            }
+            K.re[e] = tr[0];
+            K.im[e] = ti[0];
         }
     }
 
@@ -204,23 +193,24 @@ __device__ __forceinline__ void or_site(const CfgDesc &d, int p, int h, int sub,
 
 #pragma unroll
     for (int k = 0; k < L; k++) {
+        Mat<R> o;
         if (LPS == 8) {
             // the lane's one link is forward or backward at run time
-            Mat<R> f = w[k], r = w[k];
-            apply_left(f, G);
-            apply_right_dag(r, G);
+            Mat<R> f, r;
+            apply_left(w[k], G, f);
+            apply_right_dag(w[k], G, r);
 #pragma unroll
             for (int e = 0; e < 9; e++) {
-                w[k].re[e] = bwd[k] ? r.re[e] : f.re[e];
-                w[k].im[e] = bwd[k] ? r.im[e] : f.im[e];
+                o.re[e] = bwd[k] ? r.re[e] : f.re[e];
+                o.im[e] = bwd[k] ? r.im[e] : f.im[e];
             }
         } else if (bwd[k]) {
-            apply_right_dag(w[k], G);
+            apply_right_dag(w[k], G, o);
         } else {
-            apply_left(w[k], G);
+            apply_left(w[k], G, o);
         }
-        if (reunit) reunitarise(w[k]);
-        store_link<R, NE, NT>(w[k], U, g.es, off[k]);
+        if constexpr (RU) reunitarise(o);
+        store_link<R, NE, NT>(o, U, off[k]);
     }
 }
 
@@ -228,33 +218,29 @@ __device__ __forceinline__ void or_site(const CfgDesc &d, int p, int h, int sub,
 // grid-stride form was measured to double the register footprint, since
 // loop-invariant state stays live across the tile loop, so every tile gets
 // its own workgroup; the dispatcher balances the tiles over the CUs.)
-// Occupancy target: the float kernel with two lanes per site fits 2 waves per
-// SIMD (<= 256 VGPRs) without spilling only when asked to; the other
-// schedules settle at their natural register counts.
-template <typename R, int LPS> struct Waves {
-    static constexpr int lo = (sizeof(R) == 4 && LPS == 2) ? 2 : 1;
-    static constexpr int hi = (sizeof(R) == 4 && LPS == 2) ? 2 : 8;
-};
-
-template <typename R, int NE, int LPS, bool NT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(Waves<R, LPS>::lo, Waves<R, LPS>::hi)))
+template <typename R, int NE, int LPS, bool NT, bool RU>
+__global__ void __launch_bounds__(256)
 k_half_sweep(const CfgDesc *__restrict__ desc, const int *__restrict__ tile_cfg,
-             const int *__restrict__ active, int parity, int reunit) {
+             const int *__restrict__ active, int parity) {
     const int tile = blockIdx.x;
     const int c = tile_cfg[tile];
     if (!active[c]) return;
     const CfgDesc d = desc[c];
     const int h = (tile - d.tile0) * (int)(blockDim.x / LPS) + (int)(threadIdx.x / LPS);
     if (h >= d.g.Vh) return;
-    or_site<R, NE, LPS, NT>(d, parity, h, threadIdx.x % LPS, reunit);
+    or_site<R, NE, LPS, NT, RU>(d, parity, h, threadIdx.x % LPS);
 }
 
 template <typename R, int NE, int LPS, bool NT>
 static hipError_t launch_t(const Schedule &s, const CfgDesc *d_desc, const int *d_tile_cfg,
                            const int *d_active, int ntiles, int parity, int reunit, hipStream_t st) {
     if (ntiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_half_sweep<R, NE, LPS, NT>), dim3(ntiles), dim3(s.block), 0, st, d_desc,
-                       d_tile_cfg, d_active, parity, reunit);
+    if (reunit)
+        hipLaunchKernelGGL((k_half_sweep<R, NE, LPS, NT, true>), dim3(ntiles), dim3(s.block), 0, st,
+                           d_desc, d_tile_cfg, d_active, parity);
+    else
+        hipLaunchKernelGGL((k_half_sweep<R, NE, LPS, NT, false>), dim3(ntiles), dim3(s.block), 0, st,
+                           d_desc, d_tile_cfg, d_active, parity);
     return hipGetLastError();
 }
 

@@ -4,9 +4,10 @@ Argument marshalling only: torch tensors supply device memory and the HIP
 stream, every computation runs in the library's HIP kernels. Importing this
 module raises if ``libgf.so`` has not been built; there is no CPU fallback.
 
-Field tensors in the internal layout have shape (nelem, 4, 2, V/2, 2):
-[matrix element e = 3*row + col][mu][parity][h][re, im], with nelem = 9
-(18-real storage) or 6 (12-real storage), dtype float32 or float64.
+Field tensors in the internal layout have shape (2, nb, 4, nelem, 64, 2):
+[parity][block of 64 sites][mu][matrix element e = 3*row + col][site in
+block][re, im], nb = ceil(V / 128), nelem = 9 (18-real storage) or 6 (12-real
+storage), dtype float32 or float64.
 Canonical fields are complex tensors of shape (nt, nz, ny, nx, 4, 3, 3).
 """
 from __future__ import annotations
@@ -191,14 +192,20 @@ class Context:
     def field_bytes(self, i=0) -> int:
         return int(lib.gf_field_bytes(self._h, i))
 
+    BLOCK = 64
+
+    def blocks(self, i=0):
+        return (self.volume(i) // 2 + self.BLOCK - 1) // self.BLOCK
+
     def empty_field(self, i=0, device="cuda") -> torch.Tensor:
-        V = self.volume(i)
-        return torch.empty((self.nelem, 4, 2, V // 2, 2), dtype=self.rdtype, device=device)
+        # zero-filled, so the padding of the last block is deterministic
+        return torch.zeros((2, self.blocks(i), 4, self.nelem, self.BLOCK, 2), dtype=self.rdtype,
+                           device=device)
 
     def _check_field(self, U, i=0):
-        V = self.volume(i)
-        if U.dtype != self.rdtype or U.numel() != self.nelem * 4 * V * 2:
-            raise ValueError(f"field must be {self.rdtype} with {self.nelem * 8 * V} elements")
+        n = 2 * self.blocks(i) * 4 * self.nelem * self.BLOCK * 2
+        if U.dtype != self.rdtype or U.numel() != n:
+            raise ValueError(f"field must be {self.rdtype} with {n} elements")
         return _ptr(U)
 
     def pack(self, U_aos: torch.Tensor, U: torch.Tensor | None = None) -> torch.Tensor:

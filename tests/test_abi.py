@@ -62,17 +62,26 @@ def canonical_halfindex(dims, x, y, z, t):
     return (x + nx * (y + ny * (z + nz * t))) // 2
 
 
-@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (4, 6, 2, 8), (6, 2, 4, 2), (8, 4, 6, 4)])
+def layout_offset(dims, mu, p, h, ne=9):
+    """Element-0 offset of U_mu at site (p, h) in the documented blocked layout."""
+    Vh = dims[0] * dims[1] * dims[2] * dims[3] // 2
+    nb = (Vh + 63) // 64
+    return (((p * nb + h // 64) * 4 + mu) * ne) * 64 + h % 64
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 4, 4, 4), (4, 6, 2, 8), (6, 2, 4, 2), (8, 4, 6, 4),
+                                  (10, 6, 4, 2)])
 def test_half_sweep_touches_every_link_once(gf, dims):
     """The kernel's index math (the same inline function, run on the host):
-    over the sites of one parity the eight link offsets form a permutation of
-    all 4V links, and each is the link the paper's layout assigns to
-    U_mu(x) or U_mu(x - mu)."""
+    over the sites of one parity the eight links form a permutation of all
+    4V links, and each is the link that the layout assigns to U_mu(x) or
+    U_mu(x - mu)."""
     nx, ny, nz, nt = dims
     V = nx * ny * nz * nt
-    Vh = V // 2
+    all_links = {layout_offset(dims, mu, p, h) for mu in range(4) for p in (0, 1) for h in range(V // 2)}
+    assert len(all_links) == 4 * V
     for p in (0, 1):
-        seen = np.zeros(4 * V, dtype=np.int64)
+        seen = []
         sites = [(x, y, z, t) for t in range(nt) for z in range(nz) for y in range(ny) for x in range(nx)
                  if (x + y + z + t) % 2 == p]
         for (x, y, z, t) in sites:
@@ -80,13 +89,12 @@ def test_half_sweep_touches_every_link_once(gf, dims):
             offs = gf.site_links(dims, p, h)
             c = [x, y, z, t]
             for mu in range(4):
-                assert offs[mu] == mu * V + p * Vh + h
+                assert offs[mu] == layout_offset(dims, mu, p, h)
                 b = list(c)
                 b[mu] = (b[mu] - 1) % dims[mu]
-                assert offs[4 + mu] == mu * V + (1 - p) * Vh + canonical_halfindex(dims, *b)
-            for o in offs:
-                seen[o] += 1
-        assert np.all(seen == 1)
+                assert offs[4 + mu] == layout_offset(dims, mu, 1 - p, canonical_halfindex(dims, *b))
+            seen += offs
+        assert sorted(seen) == sorted(all_links)
 
 
 def test_kernel_trig_matches_libm(gf):

@@ -63,12 +63,14 @@ def test_pack_roundtrip(gf, field_cache, prec, storage):
 
 
 def test_internal_layout_positions(gf, field_cache):
-    """Element (r, c) of U_mu(x) sits at e*4V + mu*V + p*V/2 + (x + nx(y + ny(z + nz t)))/2."""
+    """Element (r, c) of U_mu at site (p, h) sits at
+    (((p nb + h / 64) 4 + mu) ne + 3r + c) 64 + h % 64, h = (x + nx(y + ny(z + nz t)))/2."""
     dims = (4, 2, 6, 2)
     nx, ny, nz, nt = dims
     U = field_cache(dims, 0.5, 2)
     ctx = make_ctx(gf, dims, LANDAU, 0)
-    I = to_gpu(ctx, U).cpu().numpy()  # (9, 4, 2, V/2, 2)
+    I = to_gpu(ctx, U).cpu().numpy().reshape(-1, 2)
+    nb = ctx.blocks()
     for t in range(nt):
         for z in range(nz):
             for y in range(ny):
@@ -76,7 +78,8 @@ def test_internal_layout_positions(gf, field_cache):
                     p = (x + y + z + t) & 1
                     h = (x + nx * (y + ny * (z + nz * t))) // 2
                     for mu in range(4):
-                        m = I[:, mu, p, h, 0] + 1j * I[:, mu, p, h, 1]
+                        base = ((p * nb + h // 64) * 4 + mu) * 9 * 64 + h % 64
+                        m = I[base + 64 * np.arange(9), 0] + 1j * I[base + 64 * np.arange(9), 1]
                         np.testing.assert_array_equal(m.reshape(3, 3), U[t, z, y, x, mu])
 
 
