@@ -80,6 +80,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--nontemporal", type=int, default=-1)
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-12real", action="store_true", help="skip the 12-real FP32 storage leg")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -106,13 +107,14 @@ def main():
     torch.cuda.synchronize()
     log(f"generated in {time.perf_counter() - t:.1f} s")
 
-    def params(prec, timing):
-        return gf.default_params(prec, check_every=spp, reunit_every=10, storage=storage,
+    def params(prec, timing, store=None):
+        return gf.default_params(prec, check_every=spp, reunit_every=10,
+                                 storage=storage if store is None else store,
                                  lanes_per_site=args.lps, block_threads=args.block,
                                  nontemporal=args.nontemporal, timing=timing)
 
-    def timed_run(prec):
-        ctx = gf.Context(dims, gauge=gf.LANDAU, prec=prec, params=params(prec, 1))
+    def timed_run(prec, store=None):
+        ctx = gf.Context(dims, gauge=gf.LANDAU, prec=prec, params=params(prec, 1, store))
         U = ctx.pack(U64 if prec == gf.F64 else U64.to(torch.complex64))
         F0, th0 = ctx.quality(U)
         for _ in range(args.warmup):
@@ -135,8 +137,8 @@ def main():
         return dict(wall=wall, kernel_ms=ms, launches=nl, F=F, theta=th, F0=F0, theta0=th0, schedule=sched)
 
 
-    def roofline(res, prec):
-        lb = args.storage * (4 if prec == gf.F32 else 8)  # bytes of one stored link
+    def roofline(res, prec, reals=None):
+        lb = (reals or args.storage) * (4 if prec == gf.F32 else 8)  # bytes of one stored link
         per_site = 16 * lb                                # 8 links read + 8 written per site update
         per_launch = per_site * (V // 2)
         avg = res["kernel_ms"] / 1e3 / res["launches"]
@@ -187,6 +189,21 @@ def main():
         },
     }
 
+    if args.storage == 18 and not args.no_12real:
+        log("timed FP32 run, 12-real storage (rows 0, 1 stored, row 2 rebuilt)")
+        r12 = timed_run(gf.F32, gf.STORE_12)
+        rf12 = roofline(r12, gf.F32, 12)
+        out["fp32_12real"] = {
+            "value": V * spp * args.steps / r12["wall"],
+            "unit": "site-sweeps/s",
+            "achieved_gbs": rf12["achieved_gbs"],
+            "frac": rf12["achieved_gbs"] / PEAK_HBM_GBS,
+            "algorithmic_bytes_per_launch": rf12["bytes_per_launch"],
+            "avg_launch_us": rf12["avg_launch_s"] * 1e6,
+            "traffic": measured_traffic(f"halfsweep_{'x'.join(map(str, dims))}_f32_12real_pmc.txt", khash),
+            "schedule": r12["schedule"],
+        }
+
     if not args.no_fp64:
         log("timed FP64 run (plain FP64 GPU form)")
         r64 = timed_run(gf.F64)
@@ -213,6 +230,18 @@ def main():
             torch.cuda.synchronize()
             conv[name] = dict(seconds=time.perf_counter() - t0, sweeps=r["iters"], converged=r["converged"],
                               F=r["F"], theta=r["theta"])
+            del U, ctx
+            torch.cuda.empty_cache()
+        for w in (1.5, 1.9):
+            log(f"fp32 run to theta < 1e-7 at omega {w}")
+            ctx = gf.Context(dims, gauge=gf.LANDAU, prec=gf.F32, params=params(gf.F32, 0))
+            U = ctx.pack(U64.to(torch.complex64))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.fix(U, w, 1e-7, 20000)
+            torch.cuda.synchronize()
+            conv[f"fp32_omega_{w}"] = dict(seconds=time.perf_counter() - t0, sweeps=r["iters"],
+                                           converged=r["converged"], F=r["F"], theta=r["theta"])
             del U, ctx
             torch.cuda.empty_cache()
         conv["fp32_speedup_to_theta_1e-7"] = conv["fp64"]["seconds"] / conv["fp32"]["seconds"]
