@@ -65,6 +65,84 @@ def measured_traffic(profile_name, khash):
         return None
 
 
+def run_ensemble(args, gf, synth, torch, np):
+    """Batching line: one Coulomb 48^3 x 96 lattice (amp 0.6, seed 0) and 64
+    Landau lattices with volumes drawn uniformly from {8^4, 12^4, 16^4, 20^4,
+    24^4} (seed 0; member i seed 1 + i, amp 0.6), FP32 links, omega 1.7, all
+    fixed to theta < 1e-7 together (check every 10 sweeps, reunitarisation
+    every 10, each check period one hipGraph replay, autotuned schedule).
+    Compared with fixing the members one after another, in FP32 and FP64."""
+    rng = np.random.default_rng(0)
+    sides = rng.choice([8, 12, 16, 20, 24], size=64)
+    members = [((48, 48, 48, 96), gf.COULOMB, 0.6, 0)] + \
+              [((int(L),) * 4, gf.LANDAU, 0.6, 1 + i) for i, L in enumerate(sides)]
+    vols = [d[0] * d[1] * d[2] * d[3] for d, _, _, _ in members]
+    eps, omega, max_iter = 1e-7, 1.7, 10000
+    log(f"ensemble: {len(members)} members, {sum(vols)} sites; generating")
+    fields = []
+    for d, g, amp, seed in members:
+        fields.append(synth.random_gauge_field(d, amp, seed, device="cuda"))
+    torch.cuda.synchronize()
+
+    def kw(prec, graph):
+        return gf.default_params(prec, check_every=10, reunit_every=10, use_graph=graph)
+
+    out = {"workload": "ensemble: Coulomb 48x48x48x96 + 64 Landau lattices in {8,12,16,20,24}^4, FP32 links, "
+                       "amp 0.6, omega 1.7, theta < 1e-7",
+           "members": len(members), "sites": sum(vols)}
+    # batched, autotuned, graphs
+    ens = gf.Context(None, prec=gf.F32, params=kw(gf.F32, 1), ensemble=[(d, g) for d, g, _, _ in members])
+    singles = [gf.Context(d, gauge=g, prec=gf.F32, params=kw(gf.F32, 0)) for d, g, _, _ in members]
+    Us = [c.pack(f.to(torch.complex64)) for c, f in zip(singles, fields)]
+    log("autotuning the ensemble schedule")
+    t0 = time.perf_counter()
+    sched = ens.autotune(Us, omega)
+    out["autotune_seconds"] = time.perf_counter() - t0
+    out["schedule"] = sched
+    Ub = [u.clone() for u in Us]
+    torch.cuda.synchronize()
+    log("batched fix")
+    t0 = time.perf_counter()
+    rb = ens.batch_fix(Ub, omega, eps, max_iter)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    sweeps = sum(it * v for it, v in zip(rb["iters"], vols))
+    out["batched"] = dict(seconds=tb, all_converged=rb["converged"], site_sweeps=sweeps,
+                          site_sweeps_per_s=sweeps / tb, iters_coulomb=rb["iters"][0],
+                          iters_landau_min=min(rb["iters"][1:]), iters_landau_max=max(rb["iters"][1:]),
+                          max_theta=max(rb["theta"]))
+    # the same members one after another (FP32, default schedule, no graphs)
+    log("sequential FP32 fixes")
+    Us32 = [u.clone() for u in Us]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r32 = [c.fix(u, omega, eps, max_iter) for c, u in zip(singles, Us32)]
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(Ub, Us32))  # every schedule gives the same bits
+    out["sequential_fp32"] = dict(seconds=t32, iters_equal=[r["iters"] for r in r32] == rb["iters"],
+                                  bitwise_equal_fields=same)
+    del Us32
+    log("sequential FP64 fixes")
+    c64 = [gf.Context(d, gauge=g, prec=gf.F64, params=kw(gf.F64, 0)) for d, g, _, _ in members]
+    t64 = 0.0
+    F64 = []
+    for c, f in zip(c64, fields):
+        u = c.pack(f)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = c.fix(u, omega, eps, max_iter)
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t0
+        F64.append(r["F"])
+        del u
+    out["sequential_fp64"] = dict(seconds=t64)
+    out["batched_speedup_vs_sequential_fp32"] = t32 / tb
+    out["batched_speedup_vs_sequential_fp64"] = t64 / tb
+    out["max_abs_F_fp32_batched_minus_fp64"] = max(abs(a - b) for a, b in zip(rb["F"], F64))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -83,6 +161,8 @@ def main():
     ap.add_argument("--no-12real", action="store_true", help="skip the 12-real FP32 storage leg")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=["single", "ensemble"], default="single",
+                    help="ensemble: Coulomb 48^3x96 plus 64 Landau lattices of uneven volume fixed together")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch one plain 1 GiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -96,6 +176,10 @@ def main():
     import torch
 
     from paper_1412_1498_amd import gf, synth
+
+    if args.workload == "ensemble":
+        print(json.dumps(run_ensemble(args, gf, synth, torch, np)), flush=True)
+        return
 
     dims = tuple(int(x) for x in args.dims.split(","))
     V = dims[0] * dims[1] * dims[2] * dims[3]

@@ -265,3 +265,62 @@ def test_full_size_48_fp32_sampled_sites(gf, oracle_lib):
             np.testing.assert_allclose(Bg[b, mu], Bo[b, mu], atol=5e-6)
     L = Bg[sites].reshape(-1, 3, 3)
     assert np.abs(L @ L.conj().transpose(0, 2, 1) - np.eye(3)).max() < 2e-6
+
+
+def test_autotune_keeps_bits_and_caches(gf, field_cache, tmp_path):
+    """The autotuner picks a schedule, the result is bitwise that of the
+    default schedule, and a cached choice is reused."""
+    members = [((8, 8, 8, 8), LANDAU, 0.5, 40), ((6, 4, 4, 2), COULOMB, 0.5, 41)]
+    prec = 1
+    ens = gf.Context(None, prec=prec, params=gf.default_params(prec, reunit_every=3),
+                     ensemble=[(d, g) for d, g, _, _ in members])
+    Us = []
+    for d, g, amp, seed in members:
+        c1 = make_ctx(gf, d, g, prec)
+        Us.append(to_gpu(c1, field_cache(d, amp, seed)))
+    ref = [u.clone() for u in Us]
+    cache = str(tmp_path / "tune.txt")
+    s1 = ens.autotune(Us, 1.7, cache)
+    assert s1["lanes_per_site"] in (1, 2, 4, 8) and s1["block_threads"] in (64, 128, 256)
+    for u, r in zip(Us, ref):  # tuning ran on scratch copies
+        assert torch.equal(u, r)
+    rb = ens.batch_fix(Us, 1.7, 0.0, 7)
+    for i, (d, g, _, _) in enumerate(members):
+        c1 = make_ctx(gf, d, g, prec, reunit_every=3)
+        c1.fix(ref[i], 1.7, 0.0, 7)
+        assert torch.equal(ref[i], Us[i])
+    ens2 = gf.Context(None, prec=prec, params=gf.default_params(prec), ensemble=[(d, g) for d, g, _, _ in members])
+    assert ens2.autotune(Us, 1.7, cache) == s1
+    assert open(cache).read().count("\n") == 1
+
+
+def test_precision_line_32x4(gf, oracle_lib):
+    """32^4, amp 0.5, seed 0: the FP64 GPU form reaches theta < 1e-12 and the
+    FP32 form (reunitarised every 10 sweeps) theta < 1e-7; their F agree; the
+    first FP64 sweeps follow the oracle."""
+    from paper_1412_1498_amd import synth
+    dims = (32, 32, 32, 32)
+    U = synth.random_gauge_field(dims, 0.5, 0, device="cuda")
+    c64 = make_ctx(gf, dims, LANDAU, 0, check_every=10)
+    U64 = c64.pack(U)
+    Uo = U.cpu().numpy()
+    c64.sweeps(U64, 1.7, 2)
+    for _ in range(2):
+        oracle_lib.sweep(Uo, dims, 1.7)
+    # Where a site's subgroup block is nearly degenerate (small |b|), rounding
+    # differences in b are amplified ~1/|b| in g; over 10^6 sites a few such
+    # sites show up, so the bound is on the distribution and on the maximum.
+    err = np.abs(to_host(c64, U64) - Uo)
+    assert np.quantile(err, 0.999) < 1e-14 and err.max() < 1e-11
+    c64.sweep_count = 0
+    U64 = c64.pack(U)
+    r64 = c64.fix(U64, 1.7, 1e-12, 20000)
+    c32 = make_ctx(gf, dims, LANDAU, 1, check_every=10, reunit_every=10)
+    U32 = c32.pack(U.to(torch.complex64))
+    r32 = c32.fix(U32, 1.7, 1e-7, 20000)
+    assert r64["converged"] and r64["theta"] < 1e-12
+    assert r32["converged"] and r32["theta"] < 1e-7
+    assert abs(r32["F"] - r64["F"]) < 1e-5
+    L = c32.unpack(U32).reshape(-1, 3, 3)
+    eye = torch.eye(3, dtype=L.dtype, device=L.device)
+    assert (L @ L.conj().transpose(-1, -2) - eye).abs().max().item() < 5e-6
