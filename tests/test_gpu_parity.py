@@ -311,7 +311,7 @@ def test_precision_line_32x4(gf, oracle_lib):
     # differences in b are amplified ~1/|b| in g; over 10^6 sites a few such
     # sites show up, so the bound is on the distribution and on the maximum.
     err = np.abs(to_host(c64, U64) - Uo)
-    assert np.quantile(err, 0.999) < 1e-14 and err.max() < 1e-11
+    assert np.median(err) < 5e-15 and np.quantile(err, 0.999) < 1e-13 and err.max() < 1e-11
     c64.sweep_count = 0
     U64 = c64.pack(U)
     r64 = c64.fix(U64, 1.7, 1e-12, 20000)
