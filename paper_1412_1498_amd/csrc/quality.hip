@@ -7,8 +7,9 @@
 // M = sum_nu [U_nu(x - nu) - U_nu(x)] and the site's Re Tr of its forward
 // links, all in double (float links are promoted exactly). The workgroup
 // sums its lanes with a fixed xor-butterfly and writes one partial pair.
-// Stage 2: one workgroup per member sums that member's partials, strided
-// per lane then by the same fixed butterfly, and normalises. Neither stage
+// Stage 2: one workgroup (1024 lanes) per member sums that member's
+// partials, strided per lane then by the same fixed butterfly, and
+// normalises. Neither stage
 // depends on the sweep schedule, so F and theta are bitwise reproducible.
 #include "su3_device.hpp"
 
@@ -95,7 +96,9 @@ k_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
 // One workgroup per member. With update_active: members that were active
 // get iters += swept, and are retired once theta < eps; retired members
 // keep their previous result.
-__global__ void __launch_bounds__(256)
+constexpr int QFINAL = 1024;
+
+__global__ void __launch_bounds__(QFINAL)
 k_quality_final(const CfgDesc *__restrict__ desc, const double *__restrict__ partials,
                 double *__restrict__ result, int *__restrict__ active, int *__restrict__ iters,
                 int swept, double eps, int update_active) {
@@ -103,9 +106,12 @@ k_quality_final(const CfgDesc *__restrict__ desc, const double *__restrict__ par
     if (update_active && !active[c]) return;
     const CfgDesc d = desc[c];
     double fs = 0.0, ts = 0.0;
-    for (int t = threadIdx.x; t < d.nqtiles; t += blockDim.x) {
-        fs += partials[2 * (d.qtile0 + t)];
-        ts += partials[2 * (d.qtile0 + t) + 1];
+    const double2 *pp = reinterpret_cast<const double2 *>(partials) + d.qtile0;
+#pragma unroll 4
+    for (int t = threadIdx.x; t < d.nqtiles; t += QFINAL) {
+        const double2 v = pp[t];
+        fs += v.x;
+        ts += v.y;
     }
     block_sum2(fs, ts);
     if (threadIdx.x == 0) {
@@ -142,7 +148,7 @@ hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int 
 hipError_t launch_quality_final(const CfgDesc *d_desc, int n, const double *d_partials,
                                 double *d_result, int *d_active, int *d_iters, int swept,
                                 double eps, int update_active, hipStream_t st) {
-    hipLaunchKernelGGL(k_quality_final, dim3(n), dim3(256), 0, st, d_desc, d_partials, d_result,
+    hipLaunchKernelGGL(k_quality_final, dim3(n), dim3(QFINAL), 0, st, d_desc, d_partials, d_result,
                        d_active, d_iters, swept, eps, update_active);
     return hipGetLastError();
 }

@@ -324,3 +324,82 @@ def test_precision_line_32x4(gf, oracle_lib):
     L = c32.unpack(U32).reshape(-1, 3, 3)
     eye = torch.eye(3, dtype=L.dtype, device=L.device)
     assert (L @ L.conj().transpose(-1, -2) - eye).abs().max().item() < 5e-6
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (2, 4, 2, 6), (8, 2, 2, 2)])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+def test_minimal_extents_match_oracle(gf, oracle_lib, field_cache, dims, gauge):
+    """Extent 2 makes x - mu and x + mu the same site (two distinct links)."""
+    U = field_cache(dims, 0.8, 50)
+    ctx = make_ctx(gf, dims, gauge, 0)
+    Ug = to_gpu(ctx, U)
+    Uo = U.copy()
+    for p in (0, 1, 0, 1):
+        ctx.sweep(Ug, p, 1.7)
+        oracle_lib.half_sweep(Uo, dims, p, 1.7, gauge)
+    assert np.abs(to_host(ctx, Ug) - Uo).max() < 1e-13
+    F, th = ctx.quality(Ug)
+    Fo, tho = oracle_lib.quality(Uo, dims, gauge)
+    assert abs(F - Fo) < 1e-13 and abs(th - tho) < 1e-12 * max(1.0, tho)
+
+
+def test_converged_members_do_no_sweeps(gf, field_cache):
+    """A member whose initial theta is already below eps reports 0 sweeps and
+    an unchanged field, while the others are fixed."""
+    members = [((4, 4, 4, 4), LANDAU), ((4, 4, 4, 4), LANDAU)]
+    ens = gf.Context(None, prec=0, params=gf.default_params(0, check_every=2), ensemble=members)
+    c1 = make_ctx(gf, (4, 4, 4, 4), LANDAU, 0)
+    unit = np.zeros((4, 4, 4, 4, 4, 3, 3), dtype=np.complex128)
+    unit[...] = np.eye(3)
+    Us = [to_gpu(c1, unit), to_gpu(c1, field_cache((4, 4, 4, 4), 0.3, 0))]
+    before = Us[0].clone()
+    r = ens.batch_fix(Us, 1.7, 1e-12, 2000)
+    assert r["converged"] and r["iters"][0] == 0 and r["iters"][1] > 0
+    assert torch.equal(Us[0], before) and r["F"][0] == 1.0 and r["theta"][0] == 0.0
+
+
+def test_non_finite_field_is_reported(gf, field_cache):
+    dims = (4, 4, 4, 4)
+    U = field_cache(dims, 0.3, 0)
+    U[1, 2, 3, 0, 2, 1, 1] = np.nan
+    ctx = make_ctx(gf, dims, LANDAU, 1)
+    Ug = to_gpu(ctx, U)
+    with pytest.raises(gf.GFError) as e:
+        ctx.quality(Ug)
+    assert e.value.code == gf.ENONFINITE
+    with pytest.raises(gf.GFError) as e:
+        ctx.fix(Ug, 1.7, 1e-7, 100)
+    assert e.value.code == gf.ENONFINITE
+
+
+def test_invalid_calls_are_rejected(gf, field_cache):
+    dims = (4, 4, 4, 4)
+    ctx = make_ctx(gf, dims, LANDAU, 1)
+    Ug = to_gpu(ctx, field_cache(dims, 0.3, 0))
+    for bad in (lambda: ctx.sweep(Ug, 2, 1.7), lambda: ctx.sweep(Ug, 0, 2.0), lambda: ctx.sweep(Ug, 0, 0.0),
+                lambda: ctx.fix(Ug, 1.7, -1.0, 10), lambda: ctx.fix(Ug, 1.7, 1e-7, -1)):
+        with pytest.raises(gf.GFError) as e:
+            bad()
+        assert e.value.code == gf.EINVAL
+    with pytest.raises(ValueError):
+        ctx.sweep(torch.zeros(10, device="cuda"), 0, 1.7)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_resume_is_bitwise_equal(gf, field_cache, prec):
+    """Checkpoint/resume: the state is the field plus the sweep counter (the
+    reunitarisation phase); 12 + 18 sweeps with a restart in between equal
+    30 sweeps in one go."""
+    dims = (8, 4, 4, 6)
+    U = field_cache(dims, 0.5, 51)
+    ctx = make_ctx(gf, dims, LANDAU, prec, reunit_every=7)
+    A = to_gpu(ctx, U)
+    ctx.sweeps(A, 1.7, 30)
+    B = to_gpu(ctx, U)
+    c1 = make_ctx(gf, dims, LANDAU, prec, reunit_every=7)
+    c1.sweeps(B, 1.7, 12)
+    saved = B.cpu()
+    c2 = make_ctx(gf, dims, LANDAU, prec, reunit_every=7, start_sweep=12)
+    B2 = saved.cuda()
+    c2.sweeps(B2, 1.7, 18)
+    assert torch.equal(A, B2) and c2.sweep_count == 30
