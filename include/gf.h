@@ -207,6 +207,23 @@ int gf_functional_grad(gf_ctx *ctx, const void *U, const void *s, double dF, voi
  * Asynchronous. */
 int gf_gauge_transform(gf_ctx *ctx, void *U, const void *s);
 
+/* ---- steepest descent with Fourier acceleration (Alg. 2, eqs. 7-9) -----
+ * One step on member 0: Delta(x) (eq. 3, the argument of eq. 7) is split
+ * into its 8 real su(3) components, Fourier transformed over the lattice (4D
+ * for Landau, 3D over x, y, z per time slice for Coulomb), multiplied by
+ * p^2_max / p^2 with p^2 = sum 4 sin^2(pi k / L) over the transformed axes
+ * (zero mode dropped), transformed back, and g(x) = reunit(1 + (alpha/2) X)
+ * (first-order exponential, Gram-Schmidt) is applied to every link. The
+ * first call allocates the FFT plans and about 1.5x a field of scratch
+ * (kept by the context). Asynchronous. alpha must be > 0 (0.08 in the
+ * paper). */
+int gf_sd_step(gf_ctx *ctx, void *U, double alpha);
+
+/* Alg. 2: F, theta; while theta >= eps and fewer than max_iter steps: steps,
+ * with F, theta every check_every steps. Returns GF_OK / GF_NOT_CONVERGED. */
+int gf_sd_fix(gf_ctx *ctx, void *U, double alpha, double eps, int max_iter, int *iters, double *F,
+              double *theta);
+
 /* ---- host-only checks (no device use) -----------------------------------
  * The SU(2) step of the sweep kernels evaluated on the host with the same
  * code: b = quaternion part (b0, b1, b2, b3) of a staple block, omega the

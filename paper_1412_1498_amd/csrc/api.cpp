@@ -3,6 +3,7 @@
 // (with hipGraph replay of a check period), the schedule autotuner and
 // kernel timing. All device work goes to the context's stream.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -56,6 +57,12 @@ struct gf_ctx {
     void *d_gfield = nullptr;
     double *d_fpart = nullptr;
     double *d_fout = nullptr;
+    // Fourier-accelerated steepest descent: su(3) components of Delta in
+    // lexicographic order, their spectrum, and the rocFFT plans
+    void *d_sd = nullptr;
+    void *d_spec = nullptr;
+    hipfftHandle fft_fwd = 0, fft_inv = 0, fft_t = 0;
+    bool sd_ready = false;
 };
 
 namespace {
@@ -384,6 +391,11 @@ int gf_destroy(gf_ctx *ctx) {
     (void)hipFree(ctx->d_active);
     (void)hipFree(ctx->d_ones);
     (void)hipFree(ctx->d_iters);
+    if (ctx->fft_fwd) (void)hipfftDestroy(ctx->fft_fwd);
+    if (ctx->fft_inv) (void)hipfftDestroy(ctx->fft_inv);
+    if (ctx->fft_t) (void)hipfftDestroy(ctx->fft_t);
+    (void)hipFree(ctx->d_sd);
+    (void)hipFree(ctx->d_spec);
     (void)hipFree(ctx->d_gfield);
     (void)hipFree(ctx->d_fpart);
     (void)hipFree(ctx->d_fout);
@@ -780,6 +792,127 @@ int gf_gauge_transform(gf_ctx *ctx, void *U, const void *s) {
     if ((rc = diff_prologue(ctx, U, s))) return rc;
     HIPTRY(ctx, launch_gauge_transform(ctx->prec, ctx->nelem, ctx->desc[0].g, U, ctx->d_gfield, ctx->stream));
     return GF_OK;
+}
+
+// ---- steepest descent with Fourier acceleration (Alg. 2) ----------------------
+
+namespace {
+
+#define FFTTRY(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipfftResult r_ = (call);                                                                \
+        if (r_ != HIPFFT_SUCCESS) return fail(ctx, GF_EDEVICE, "%s failed: hipfft status %d", #call, (int)r_); \
+    } while (0)
+
+// Buffers and plans: 3D real-to-complex transforms over (z, y, x) batched
+// over the 8 components and the time slices, and (Landau) a strided complex
+// 1D transform along t, applied per component.
+int sd_prepare(gf_ctx *ctx) {
+    if (ctx->sd_ready) return GF_OK;
+    int rc;
+    if ((rc = ensure_diff_scratch(ctx))) return rc;
+    const Geom &g = ctx->desc[0].g;
+    const size_t rs = ctx->prec == GF_F64 ? 8 : 4;
+    const long long S = (long long)g.nz * g.ny * (g.nx / 2 + 1);
+    if (hipMalloc(&ctx->d_sd, 8 * (size_t)g.V * rs) != hipSuccess ||
+        hipMalloc(&ctx->d_spec, 8 * (size_t)g.nt * S * 2 * rs) != hipSuccess)
+        return fail(ctx, GF_ENOMEM, "cannot allocate the Fourier acceleration buffers");
+    int n3[3] = {g.nz, g.ny, g.nx};
+    const bool dp = ctx->prec == GF_F64;
+    FFTTRY(ctx, hipfftPlanMany(&ctx->fft_fwd, 3, n3, nullptr, 1, g.nz * g.ny * g.nx, nullptr, 1, (int)S,
+                               dp ? HIPFFT_D2Z : HIPFFT_R2C, 8 * g.nt));
+    FFTTRY(ctx, hipfftPlanMany(&ctx->fft_inv, 3, n3, nullptr, 1, (int)S, nullptr, 1, g.nz * g.ny * g.nx,
+                               dp ? HIPFFT_Z2D : HIPFFT_C2R, 8 * g.nt));
+    FFTTRY(ctx, hipfftSetStream(ctx->fft_fwd, ctx->stream));
+    FFTTRY(ctx, hipfftSetStream(ctx->fft_inv, ctx->stream));
+    if (ctx->desc[0].gauge == GF_LANDAU) {
+        int nt1[1] = {g.nt};
+        FFTTRY(ctx, hipfftPlanMany(&ctx->fft_t, 1, nt1, nt1, (int)S, 1, nt1, (int)S, 1,
+                                   dp ? HIPFFT_Z2Z : HIPFFT_C2C, (int)S));
+        FFTTRY(ctx, hipfftSetStream(ctx->fft_t, ctx->stream));
+    }
+    ctx->sd_ready = true;
+    return GF_OK;
+}
+
+int sd_t_transform(gf_ctx *ctx, int dir) {
+    const Geom &g = ctx->desc[0].g;
+    const long long S = (long long)g.nz * g.ny * (g.nx / 2 + 1);
+    for (int a = 0; a < 8; a++) {
+        const long long off = (long long)a * g.nt * S;
+        if (ctx->prec == GF_F64) {
+            hipfftDoubleComplex *p = (hipfftDoubleComplex *)ctx->d_spec + off;
+            FFTTRY(ctx, hipfftExecZ2Z(ctx->fft_t, p, p, dir));
+        } else {
+            hipfftComplex *p = (hipfftComplex *)ctx->d_spec + off;
+            FFTTRY(ctx, hipfftExecC2C(ctx->fft_t, p, p, dir));
+        }
+    }
+    return GF_OK;
+}
+
+int sd_step_impl(gf_ctx *ctx, void *U, double alpha) {
+    int rc;
+    const Geom &g = ctx->desc[0].g;
+    const int gauge = ctx->desc[0].gauge;
+    const bool landau = gauge == GF_LANDAU;
+    HIPTRY(ctx, launch_sd_delta(ctx->prec, ctx->nelem, gauge, g, U, ctx->d_sd, ctx->stream));
+    if (ctx->prec == GF_F64)
+        FFTTRY(ctx, hipfftExecD2Z(ctx->fft_fwd, (hipfftDoubleReal *)ctx->d_sd, (hipfftDoubleComplex *)ctx->d_spec));
+    else
+        FFTTRY(ctx, hipfftExecR2C(ctx->fft_fwd, (hipfftReal *)ctx->d_sd, (hipfftComplex *)ctx->d_spec));
+    if (landau && (rc = sd_t_transform(ctx, HIPFFT_FORWARD))) return rc;
+    const double nfft = landau ? (double)g.V : (double)g.nx * g.ny * g.nz;
+    const double p2max = landau ? 16.0 : 12.0;
+    HIPTRY(ctx, launch_sd_filter(ctx->prec, g, landau ? 1 : 0, ctx->d_spec, 0.5 * alpha / nfft, p2max, ctx->stream));
+    if (landau && (rc = sd_t_transform(ctx, HIPFFT_BACKWARD))) return rc;
+    if (ctx->prec == GF_F64)
+        FFTTRY(ctx, hipfftExecZ2D(ctx->fft_inv, (hipfftDoubleComplex *)ctx->d_spec, (hipfftDoubleReal *)ctx->d_sd));
+    else
+        FFTTRY(ctx, hipfftExecC2R(ctx->fft_inv, (hipfftComplex *)ctx->d_spec, (hipfftReal *)ctx->d_sd));
+    HIPTRY(ctx, launch_sd_gfield(ctx->prec, g, ctx->d_sd, ctx->d_gfield, ctx->stream));
+    HIPTRY(ctx, launch_gauge_transform(ctx->prec, ctx->nelem, g, U, ctx->d_gfield, ctx->stream));
+    return GF_OK;
+}
+
+int check_alpha(gf_ctx *ctx, double alpha) {
+    CHECK(ctx, std::isfinite(alpha) && alpha > 0.0, GF_EINVAL, "alpha = %g must be finite and > 0", alpha);
+    return GF_OK;
+}
+
+}  // namespace
+
+int gf_sd_step(gf_ctx *ctx, void *U, double alpha) {
+    if (!ctx) return GF_EINVAL;
+    int rc;
+    if ((rc = need_single(ctx)) || (rc = check_field(ctx, U, "U")) || (rc = check_alpha(ctx, alpha))) return rc;
+    DeviceGuard dg(ctx->device);
+    if ((rc = sd_prepare(ctx))) return rc;
+    return sd_step_impl(ctx, U, alpha);
+}
+
+int gf_sd_fix(gf_ctx *ctx, void *U, double alpha, double eps, int max_iter, int *iters, double *F,
+              double *theta) {
+    if (!ctx) return GF_EINVAL;
+    int rc;
+    if ((rc = need_single(ctx)) || (rc = check_field(ctx, U, "U")) || (rc = check_alpha(ctx, alpha))) return rc;
+    CHECK(ctx, iters && F && theta, GF_EINVAL, "NULL argument");
+    CHECK(ctx, std::isfinite(eps) && eps >= 0.0, GF_EINVAL, "eps must be finite and >= 0");
+    CHECK(ctx, max_iter >= 0, GF_EINVAL, "max_iter must be >= 0");
+    DeviceGuard dg(ctx->device);
+    if ((rc = sd_prepare(ctx))) return rc;
+    *iters = 0;
+    if ((rc = gf_quality(ctx, U, F, theta))) return rc;
+    int it = 0;
+    while (it < max_iter && !(*theta < eps)) {
+        const int m = std::min(ctx->p.check_every, max_iter - it);
+        for (int k = 0; k < m; k++)
+            if ((rc = sd_step_impl(ctx, U, alpha))) return rc;
+        it += m;
+        *iters = it;
+        if ((rc = gf_quality(ctx, U, F, theta))) return rc;
+    }
+    return *theta < eps ? GF_OK : GF_NOT_CONVERGED;
 }
 
 // ---- host-only checks ------------------------------------------------------

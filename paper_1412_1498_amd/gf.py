@@ -83,6 +83,8 @@ def _load():
         "gf_functional": (I, [P, P, P, P]),
         "gf_functional_grad": (I, [P, P, P, D, P]),
         "gf_gauge_transform": (I, [P, P, P]),
+        "gf_sd_step": (I, [P, P, D]),
+        "gf_sd_fix": (I, [P, P, D, D, I, P, P, P]),
         "gf_host_su2_step": (None, [P, D, P]),
         "gf_host_trig": (None, [D, D, P]),
         "gf_site_links": (I, [P, I, LL, P]),
@@ -271,6 +273,17 @@ class Context:
         th = (ctypes.c_double * n)()
         self._check(lib.gf_batch_quality(self._h, self._ptr_array(Us), F, th))
         return list(F), list(th)
+
+    # -- steepest descent with Fourier acceleration (Alg. 2) --------------------
+    def sd_step(self, U, alpha=0.08):
+        self._check(lib.gf_sd_step(self._h, ctypes.c_void_p(self._check_field(U)), float(alpha)))
+
+    def sd_fix(self, U, alpha, eps, max_iter):
+        it, F, th = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
+        rc = self._check(lib.gf_sd_fix(self._h, ctypes.c_void_p(self._check_field(U)), float(alpha),
+                                       float(eps), int(max_iter), ctypes.byref(it), ctypes.byref(F),
+                                       ctypes.byref(th)), allow=(OK, NOT_CONVERGED))
+        return dict(converged=rc == OK, iters=it.value, F=F.value, theta=th.value)
 
     # -- schedule, timing -------------------------------------------------------
     def autotune(self, Us, omega, cache_path=None):

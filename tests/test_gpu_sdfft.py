@@ -1,0 +1,81 @@
+"""GPU parity of steepest descent with Fourier acceleration (Alg. 2) against
+the FP64 oracle (oracle/sdfft.py), through the C ABI.
+
+Tolerances: FP64 links after one step 1e-13 abs (the oracle transforms the
+nine complex matrix elements with numpy's FFT, the GPU the eight real su(3)
+components with rocFFT: same linear map, different rounding); FP32 5e-6
+(float FFTs and float g)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sdfft
+
+pytestmark = pytest.mark.gpu
+
+LANDAU, COULOMB = 0, 1
+
+
+@pytest.fixture(scope="module")
+def gf():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1412_1498_amd import gf as mod
+    return mod
+
+
+def setup(gf, dims, gauge, prec, U, **kw):
+    ctx = gf.Context(dims, gauge=gauge, prec=prec, params=gf.default_params(prec, **kw))
+    Ug = ctx.pack(torch.from_numpy(np.ascontiguousarray(U)).to("cuda", dtype=ctx.cdtype))
+    return ctx, Ug
+
+
+def host(ctx, Ug):
+    return ctx.unpack(Ug).cpu().numpy().astype(np.complex128)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("dims", [(4, 6, 2, 8), (8, 8, 8, 8), (6, 4, 4, 2)])
+def test_sd_step_matches_oracle(gf, field_cache, prec, gauge, dims):
+    U = field_cache(dims, 0.4, 70)
+    ctx, Ug = setup(gf, dims, gauge, prec, U)
+    Uo = U.astype(np.complex64).astype(np.complex128) if prec == 1 else U.copy()
+    for _ in range(3):
+        ctx.sd_step(Ug, 0.08)
+        Uo = sdfft.sd_step(Uo, 0.08, gauge)
+    assert np.abs(host(ctx, Ug) - Uo).max() < (1e-13 if prec == 0 else 5e-6)
+
+
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+def test_sd_fix_matches_oracle(gf, oracle_lib, field_cache, gauge):
+    dims = (8, 8, 8, 8)
+    U = field_cache(dims, 0.3, 0)
+    ctx, Ug = setup(gf, dims, gauge, 0)
+    r = ctx.sd_fix(Ug, 0.08, 1e-12, 3000)
+    Uo, ro = sdfft.sd_fix(U.copy(), dims, 0.08, 1e-12, 3000, gauge)
+    assert r["converged"] and ro["converged"] and r["theta"] < 1e-12
+    assert abs(r["iters"] - ro["iters"]) <= 1
+    assert abs(r["F"] - ro["F"]) < 1e-12
+
+
+def test_sd_fft_fp32_reaches_1e7_and_tracks_or(gf, field_cache):
+    """Alg. 2 in FP32 reaches theta < 1e-7 and lands on the same maximum as
+    overrelaxation (Alg. 1) from the same start."""
+    dims = (16, 16, 16, 16)
+    U = field_cache(dims, 0.3, 71)
+    ctx, Ug = setup(gf, dims, LANDAU, 1)
+    r = ctx.sd_fix(Ug, 0.08, 1e-7, 5000)
+    c2, U2 = setup(gf, dims, LANDAU, 1, check_every=10)
+    r2 = c2.fix(U2, 1.7, 1e-7, 20000)
+    assert r["converged"] and r2["converged"]
+    assert r["iters"] < r2["iters"]
+    assert abs(r["F"] - r2["F"]) < 1e-5
+
+
+def test_sd_rejects_bad_alpha(gf, field_cache):
+    dims = (4, 4, 4, 4)
+    ctx, Ug = setup(gf, dims, LANDAU, 1, )
+    for a in (0.0, -0.1, float("nan")):
+        with pytest.raises(gf.GFError) as e:
+            ctx.sd_step(Ug, a)
+        assert e.value.code == gf.EINVAL
