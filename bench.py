@@ -161,6 +161,7 @@ def main():
     ap.add_argument("--no-12real", action="store_true", help="skip the 12-real FP32 storage leg")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-diff", action="store_true", help="skip the differentiation timing leg")
     ap.add_argument("--workload", choices=["single", "ensemble"], default="single",
                     help="ensemble: Coulomb 48^3x96 plus 64 Landau lattices of uneven volume fixed together")
     ap.add_argument("--copy-probe", action="store_true",
@@ -345,6 +346,36 @@ def main():
         conv["abs_F_fp32_minus_fp64"] = abs(conv["fp32"]["F"] - conv["fp64"]["F"])
         conv["theta_convention"] = "literal eq. (3): A = M - M^+, minus trace/3, no 1/2 or 1/(2i)"
         out["convergence"] = conv
+
+    if not args.no_diff:
+        # differentiation line: F_U[g] and its hand-written backward at 24^4
+        # (amp 0.4, s_a ~ N(0, 0.1^2)), FP32 and FP64
+        ddims = (24, 24, 24, 24)
+        Vd = 24 ** 4
+        Ud = synth.random_gauge_field(ddims, 0.4, 0, device="cuda")
+        sd = synth.random_algebra_field(ddims, 0.1, 1)
+        diffres = {}
+        for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
+            ctx = gf.Context(ddims, gauge=gf.LANDAU, prec=prec)
+            U = ctx.pack(Ud.to(ctx.cdtype))
+            s = ctx.pack_alg(sd.to("cuda", dtype=ctx.rdtype))
+            grad = ctx.functional_grad(U, s)
+            ctx.functional(U, s)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(20):
+                ctx.functional(U, s)
+            tf = (time.perf_counter() - t0) / 20
+            t0 = time.perf_counter()
+            for _ in range(20):
+                ctx.functional_grad(U, s, 1.0, out=grad)
+            torch.cuda.synchronize()
+            tb = (time.perf_counter() - t0) / 20
+            diffres[name] = dict(forward_ms=tf * 1e3, backward_ms=tb * 1e3, sites_per_s_backward=Vd / tb)
+            del U, s, grad, ctx
+        out["differentiation_24x4"] = diffres
+        del Ud
+        torch.cuda.empty_cache()
 
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
