@@ -50,7 +50,7 @@ def test_sd_step_matches_oracle(gf, field_cache, prec, gauge, dims):
 def test_sd_fix_matches_oracle(gf, oracle_lib, field_cache, gauge):
     dims = (8, 8, 8, 8)
     U = field_cache(dims, 0.3, 0)
-    ctx, Ug = setup(gf, dims, gauge, 0)
+    ctx, Ug = setup(gf, dims, gauge, 0, U)
     r = ctx.sd_fix(Ug, 0.08, 1e-12, 3000)
     Uo, ro = sdfft.sd_fix(U.copy(), dims, 0.08, 1e-12, 3000, gauge)
     assert r["converged"] and ro["converged"] and r["theta"] < 1e-12
@@ -63,9 +63,9 @@ def test_sd_fft_fp32_reaches_1e7_and_tracks_or(gf, field_cache):
     overrelaxation (Alg. 1) from the same start."""
     dims = (16, 16, 16, 16)
     U = field_cache(dims, 0.3, 71)
-    ctx, Ug = setup(gf, dims, LANDAU, 1)
+    ctx, Ug = setup(gf, dims, LANDAU, 1, U)
     r = ctx.sd_fix(Ug, 0.08, 1e-7, 5000)
-    c2, U2 = setup(gf, dims, LANDAU, 1, check_every=10)
+    c2, U2 = setup(gf, dims, LANDAU, 1, U, check_every=10)
     r2 = c2.fix(U2, 1.7, 1e-7, 20000)
     assert r["converged"] and r2["converged"]
     assert r["iters"] < r2["iters"]
@@ -74,7 +74,7 @@ def test_sd_fft_fp32_reaches_1e7_and_tracks_or(gf, field_cache):
 
 def test_sd_rejects_bad_alpha(gf, field_cache):
     dims = (4, 4, 4, 4)
-    ctx, Ug = setup(gf, dims, LANDAU, 1, )
+    ctx, Ug = setup(gf, dims, LANDAU, 1, field_cache(dims, 0.3, 0))
     for a in (0.0, -0.1, float("nan")):
         with pytest.raises(gf.GFError) as e:
             ctx.sd_step(Ug, a)
