@@ -58,7 +58,7 @@ struct gf_ctx {
     double *d_fpart = nullptr;
     double *d_fout = nullptr;
     // Fourier-accelerated steepest descent: su(3) components of Delta in
-    // lexicographic order, their spectrum, and the rocFFT plans
+    // lexicographic order, their spectrum, and the hipFFT plans
     void *d_sd = nullptr;
     void *d_spec = nullptr;
     hipfftHandle fft_fwd = 0, fft_inv = 0, fft_t = 0;
@@ -307,7 +307,7 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
         d.gauge = gauge[c];
         d.omega = 1.0;
         d.qtile0 = nq;
-        d.nqtiles = (d.g.V + QTILE - 1) / QTILE;
+        d.nqtiles = (d.g.Vh + QTILE / 2 - 1) / (QTILE / 2);  // QTILE/2 half-indices, both parities
         nq += d.nqtiles;
     }
     ctx->nqtiles = nq;

@@ -1,12 +1,17 @@
 // quality.hip -- F (eq. 1) and theta (eqs. 2-3) of every ensemble member,
 // reduced in double in a fixed order.
 //
-// Stage 1: one workgroup per tile of QTILE consecutive sites (site index
-// n = p*V/2 + h over both parities); each lane reads the eight links of its
-// site, forms Delta(x) = A - (Tr A / 3) 1 with A = M - M^dagger,
-// M = sum_nu [U_nu(x - nu) - U_nu(x)] and the site's Re Tr of its forward
-// links, all in double (float links are promoted exactly). The workgroup
-// sums its lanes with a fixed xor-butterfly and writes one partial pair.
+// Stage 1: one workgroup per tile of QTILE sites: the QTILE/2 half-indices
+// h of the tile, both parities (lanes [0, QTILE/2) even, the rest odd). A
+// site's backward links belong to the other parity at nearby h (x, y, z
+// neighbours), so the tile's own forward reads bring most of them into
+// cache; tiles are also handed out so that each XCD walks one contiguous
+// range of h (its L2 then still holds the z neighbours). Each lane reads the
+// eight links of its site, forms Delta(x) = A - (Tr A / 3) 1 with
+// A = M - M^dagger, M = sum_nu [U_nu(x - nu) - U_nu(x)] and the site's Re Tr
+// of its forward links, all in double (float links are promoted exactly).
+// The workgroup sums its lanes with a fixed xor-butterfly and writes one
+// partial pair.
 // Stage 2: one workgroup (1024 lanes) per member sums that member's
 // partials, strided per lane then by the same fixed butterfly, and
 // normalises. Neither stage
@@ -39,21 +44,31 @@ __device__ __forceinline__ void block_sum2(double &a, double &b) {
     }
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by id. Map id b of n
+// to a tile so that XCD k gets the k-th contiguous share of the tiles, in
+// order (a bijection of [0, n) for any n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+    constexpr int NX = 8;
+    const int x = b % NX, i = b / NX;
+    const int q = n / NX, r = n % NX;
+    return x * q + min(x, r) + i;
+}
+
 template <typename R, int NE>
 __global__ void __launch_bounds__(QTILE)
 k_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
           const int *__restrict__ active, double *__restrict__ partials) {
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
     const int c = qtile_cfg[tile];
     if (active && !active[c]) return;
     const CfgDesc d = desc[c];
     const Geom &g = d.g;
-    const int n = (tile - d.qtile0) * QTILE + threadIdx.x;
+    constexpr int QH = QTILE / 2;
+    const int p = threadIdx.x >= QH;
+    const int h = (tile - d.qtile0) * QH + (int)threadIdx.x - p * QH;
     const int nd = d.gauge == 0 ? 4 : 3;
     double fsum = 0.0, tsum = 0.0;
-    if (n < g.V) {
-        const int p = n >= g.Vh;
-        const int h = n - p * g.Vh;
+    if (h < g.Vh) {
         const SiteNbr nb = site_neighbours(g, p, h);
         const gchar *U = as_global(d.U);
         double mr[9], mi[9];

@@ -3,7 +3,7 @@
 // lexicographic site order (the FFT input), the p^2_max / p^2 filter applied
 // in momentum space, and the first-order gauge transformation
 // g(x) = reunit(1 + (alpha/2) F^-1[...] Delta) written as a g field for
-// k_gauge_transform. The FFTs themselves are rocFFT calls made by the host.
+// k_gauge_transform. The FFTs themselves are hipFFT calls made by the host.
 //
 // Delta is anti-hermitian and traceless: Delta = i sum_a d_a lambda_a with
 // d_a = Tr[lambda_a Delta] / (2i) real, so filtering the eight real d_a is

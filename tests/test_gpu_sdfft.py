@@ -3,7 +3,7 @@ the FP64 oracle (oracle/sdfft.py), through the C ABI.
 
 Tolerances: FP64 links after one step 1e-13 abs (the oracle transforms the
 nine complex matrix elements with numpy's FFT, the GPU the eight real su(3)
-components with rocFFT: same linear map, different rounding); FP32 5e-6
+components with hipFFT: same linear map, different rounding); FP32 5e-6
 (float FFTs and float g)."""
 import numpy as np
 import pytest
