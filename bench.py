@@ -72,10 +72,7 @@ def run_ensemble(args, gf, synth, torch, np):
     fixed to theta < 1e-7 together (check every 10 sweeps, reunitarisation
     every 10, each check period one hipGraph replay, autotuned schedule).
     Compared with fixing the members one after another, in FP32 and FP64."""
-    rng = np.random.default_rng(0)
-    sides = rng.choice([8, 12, 16, 20, 24], size=64)
-    members = [((48, 48, 48, 96), gf.COULOMB, 0.6, 0)] + \
-              [((int(L),) * 4, gf.LANDAU, 0.6, 1 + i) for i, L in enumerate(sides)]
+    members = synth.ensemble_members(64, seed=0, amp=0.6)
     vols = [d[0] * d[1] * d[2] * d[3] for d, _, _, _ in members]
     eps, omega, max_iter = 1e-7, 1.7, 10000
     log(f"ensemble: {len(members)} members, {sum(vols)} sites; generating")

@@ -141,3 +141,15 @@ def random_algebra_field(dims, sigma: float, seed: int) -> torch.Tensor:
     rng = np.random.Generator(np.random.PCG64(seed))
     s = rng.standard_normal((nt, nz, ny, nx, 8)) * sigma
     return torch.from_numpy(s)
+
+
+def ensemble_members(n_landau: int = 64, seed: int = 0, amp: float = 0.6):
+    """The uneven ensemble: one Coulomb-gauge 48^3 x 96 lattice (field seed 0)
+    and n_landau Landau-gauge lattices whose sides are drawn uniformly from
+    {8, 12, 16, 20, 24} with numpy PCG64(seed); member i uses field seed
+    1 + i. Returns [(dims (nx, ny, nz, nt), gauge 0 Landau / 1 Coulomb, amp,
+    field seed)]."""
+    rng = np.random.default_rng(seed)
+    sides = rng.choice([8, 12, 16, 20, 24], size=n_landau)
+    return [((48, 48, 48, 96), 1, amp, 0)] + \
+           [((int(L),) * 4, 0, amp, 1 + i) for i, L in enumerate(sides)]

@@ -44,7 +44,43 @@ def oracle_input(U_np, prec):
     return U_np.astype(np.complex64).astype(np.complex128) if prec == 1 else U_np.copy()
 
 
-DIMS = [(4, 4, 4, 4), (4, 6, 2, 8), (6, 4, 4, 2), (8, 8, 8, 8)]
+# (8, 6, 8, 8): 12 quality tiles, not a multiple of the 8 XCDs the tiles are dealt to
+DIMS = [(4, 4, 4, 4), (4, 6, 2, 8), (6, 4, 4, 2), (8, 8, 8, 8), (8, 6, 8, 8)]
+
+
+def neighbour(dims, s, mu, sign):
+    """Lexicographic index of x + sign * mu-hat (periodic)."""
+    nx, ny, nz, nt = dims
+    c = [s % nx, (s // nx) % ny, (s // (nx * ny)) % nz, s // (nx * ny * nz)]
+    c[mu] = (c[mu] + sign) % dims[mu]
+    return c[0] + nx * (c[1] + ny * (c[2] + nz * c[3]))
+
+
+def oracle_full_sweep_at(oracle_lib, Uo, dims, odd_sites, omega, gauge):
+    """The eight links of each given odd site after one full sweep, computed
+    in place on Uo: an odd site's links are each changed by exactly one even
+    neighbour in the even half-sweep, then by the site itself; even sites are
+    independent of each other, so updating only the even neighbours of the
+    sampled sites (each once, all before any odd update) gives exactly the
+    even half-sweep's values on those links."""
+    evens = []
+    for s in odd_sites:
+        for mu in range(4):
+            for sign in (1, -1):
+                e = neighbour(dims, s, mu, sign)
+                if e not in evens:
+                    evens.append(e)
+    for e in evens:
+        oracle_lib.site_update(Uo, dims, e, omega, gauge)
+    for s in odd_sites:
+        oracle_lib.site_update(Uo, dims, s, omega, gauge)
+
+
+def site_links(U, dims, s):
+    """(8, 3, 3): U_mu(x) for mu = 0..3, then U_mu(x - mu) for mu = 0..3."""
+    V = int(np.prod(dims))
+    B = U.reshape(V, 4, 3, 3)
+    return np.stack([B[s, mu] for mu in range(4)] + [B[neighbour(dims, s, mu, -1), mu] for mu in range(4)])
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -228,43 +264,89 @@ def test_timing_counts_half_sweeps(gf, field_cache, prec):
     assert n == 10 and ms > 0
 
 
-def test_full_size_48_fp32_sampled_sites(gf, oracle_lib):
-    """48^4, amp 0.7, FP32 links, the default schedule: after one even
-    half-sweep on the GPU, every sampled even site's eight links equal the
-    oracle's single-site update of the same (double-promoted) links; F does
-    not decrease; unitarity holds."""
+@pytest.mark.parametrize("prec", [1, 0])
+def test_full_size_48_sampled_sites(gf, oracle_lib, prec):
+    """48^4, amp 0.7, the default schedule (the bench's launch configuration),
+    FP32 and FP64 links: F and theta of the whole field equal the oracle's;
+    after one even half-sweep on the GPU every sampled even site's eight
+    links equal the oracle's single-site update of the same (for FP32:
+    double-promoted) links; F does not decrease; unitarity holds.
+
+    F/theta tolerance 1e-10 relative: the oracle adds ~2e7 terms of one sign
+    one after another (rounding error bound N u = 2e-9, random-walk size
+    sqrt(N) u = 5e-13), the GPU in a fixed tree."""
     from paper_1412_1498_amd import synth
     dims = (48, 48, 48, 48)
     U64 = synth.random_gauge_field(dims, 0.7, 0, device="cuda")
-    U32 = U64.to(torch.complex64)
-    del U64
-    ctx = make_ctx(gf, dims, LANDAU, 1)
-    Ug = ctx.pack(U32)
-    F0, _ = ctx.quality(Ug)
-    Uo = U32.cpu().numpy().astype(np.complex128)
-    del U32
+    Uc = U64.to(torch.complex64) if prec == 1 else U64
+    if prec == 1:
+        del U64
+    ctx = make_ctx(gf, dims, LANDAU, prec)
+    Ug = ctx.pack(Uc)
+    F0, th0 = ctx.quality(Ug)
+    Uo = Uc.cpu().numpy().astype(np.complex128)
+    del Uc
+    Fo, tho = oracle_lib.quality(Uo, dims, LANDAU)
+    assert abs(F0 - Fo) <= 1e-10 * abs(Fo) and abs(th0 - tho) <= 1e-10 * tho
     ctx.sweep(Ug, 0, 1.7)
     F1, _ = ctx.quality(Ug)
     assert F1 >= F0
-    back = ctx.unpack(Ug).cpu().numpy()
+    back = ctx.unpack(Ug).cpu().numpy().astype(np.complex128)
     rng = np.random.default_rng(0)
     V = 48 ** 4
     par = oracle_lib.parity_of_sites(dims)
-    sites = [s for s in rng.choice(V, 400, replace=False) if par[s] == 0][:128]
+    sites = [int(s) for s in rng.choice(V, 400, replace=False) if par[s] == 0][:128]
     for s in sites:
-        oracle_lib.site_update(Uo, dims, int(s), 1.7)
-    Bo = Uo.reshape(V, 4, 3, 3)
-    Bg = back.reshape(V, 4, 3, 3)
-    nx = 48
+        oracle_lib.site_update(Uo, dims, s, 1.7)
+    tol = 5e-6 if prec == 1 else 1e-13
     for s in sites:
-        np.testing.assert_allclose(Bg[s], Bo[s], atol=5e-6)
-        x, y, z, t = s % nx, (s // nx) % nx, (s // nx ** 2) % nx, s // nx ** 3
-        for mu, step in enumerate([1, nx, nx ** 2, nx ** 3]):
-            c = [x, y, z, t][mu]
-            b = s - step if c > 0 else s + (nx - 1) * step
-            np.testing.assert_allclose(Bg[b, mu], Bo[b, mu], atol=5e-6)
-    L = Bg[sites].reshape(-1, 3, 3)
-    assert np.abs(L @ L.conj().transpose(0, 2, 1) - np.eye(3)).max() < 2e-6
+        np.testing.assert_allclose(site_links(back, dims, s), site_links(Uo, dims, s), atol=tol)
+    L = np.concatenate([site_links(back, dims, s) for s in sites])
+    assert np.abs(L @ L.conj().transpose(0, 2, 1) - np.eye(3)).max() < (2e-6 if prec == 1 else 1e-13)
+
+
+def test_full_size_ensemble_sampled_sites(gf, oracle_lib):
+    """The uneven ensemble at full size (Coulomb 48^3 x 96 + 64 Landau
+    lattices of sides 8..24, amp 0.6, FP32 links) in one context, as the
+    ensemble bench runs it (graph replay): every member's F and theta equal
+    the oracle's; after one batched sweep (Alg. 1 with max_iter 1) the eight
+    links of sampled odd sites of the Coulomb member and of three Landau
+    members equal the oracle's sweep at those sites.
+
+    Link tolerance 2e-5: two half-sweeps applied in float (5e-6 each, see the
+    module notes), the second on inputs that already carry the first's
+    rounding. F/theta: 1e-10 relative (as at 48^4)."""
+    from paper_1412_1498_amd import synth
+    members = synth.ensemble_members(64, seed=0, amp=0.6)
+    prec = 1
+    ens = gf.Context(None, prec=prec, params=gf.default_params(prec, check_every=1, reunit_every=1000, use_graph=1),
+                     ensemble=[(d, g) for d, g, _, _ in members])
+    Us, host = [], []
+    for i, (d, g, amp, seed) in enumerate(members):
+        u = synth.random_gauge_field(d, amp, seed, device="cuda").to(torch.complex64)
+        c1 = make_ctx(gf, d, g, prec)
+        Us.append(c1.pack(u))
+        host.append(u.cpu().numpy().astype(np.complex128))
+        del u
+    F, th = ens.batch_quality(Us)
+    for i, (d, g, _, _) in enumerate(members):
+        Fo, tho = oracle_lib.quality(host[i], d, g)
+        assert abs(F[i] - Fo) <= 1e-10 * abs(Fo) and abs(th[i] - tho) <= 1e-10 * tho, i
+    r = ens.batch_fix(Us, 1.7, 0.0, 1)
+    assert r["iters"] == [1] * len(members)
+    rng = np.random.default_rng(1)
+    checked = [0] + [int(i) for i in rng.choice(np.arange(1, len(members)), 3, replace=False)]
+    for i in checked:
+        d, g, _, _ = members[i]
+        V = int(np.prod(d))
+        par = oracle_lib.parity_of_sites(d)
+        sites = [int(s) for s in rng.choice(V, 200, replace=False) if par[s] == 1][:32]
+        oracle_full_sweep_at(oracle_lib, host[i], d, sites, 1.7, g)
+        c1 = make_ctx(gf, d, g, prec)
+        back = c1.unpack(Us[i]).cpu().numpy().astype(np.complex128)
+        for s in sites:
+            np.testing.assert_allclose(site_links(back, d, s), site_links(host[i], d, s), atol=2e-5,
+                                       err_msg=f"member {i} site {s}")
 
 
 def test_autotune_keeps_bits_and_caches(gf, field_cache, tmp_path):
