@@ -6,6 +6,8 @@ nothing from it.
 
 * ``gf_oracle.c`` -- Alg. 1 (overrelaxation with even/odd sites), eqs. (1)-(6),
   reunitarisation; plain C99 loops in double precision.
+* ``gf_oracle_sun.c`` / ``sun.py`` -- the same for SU(N), N >= 2 (all N(N-1)/2
+  SU(2) subgroups).
 * ``diff.py`` -- the functional F_U[g] as a function of g(x) = exp(S(x)) and its
   gradient by eigendecomposition (numpy), plus the steepest-descent step of
   eq. (7).
@@ -15,3 +17,4 @@ from .core import (  # noqa: F401
     subgroup_update, site_update, half_sweep, half_sweep_order, sweep,
     reunit, fix, parity_of_sites,
 )
+from . import sun  # noqa: F401

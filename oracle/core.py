@@ -14,6 +14,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gf_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "gf_oracle_sun.c")]
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
@@ -22,10 +23,10 @@ LANDAU, COULOMB = 0, 1
 
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain -O2, no FP contraction)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + f".tmp{os.getpid()}"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99",
-                               "-o", tmp, _SRC, "-lm"])
+                               "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -49,6 +50,18 @@ def load():
         lib.oracle_reunit.argtypes = [P, L]
         lib.oracle_fix.argtypes = [P, P, I, D, D, I, I, I, L, P, P, P]
         lib.oracle_fix.restype = I
+        lib.oracle_sun_quality.argtypes = [P, P, I, I, P, P]
+        lib.oracle_sun_staple.argtypes = [P, P, I, I, L, P]
+        lib.oracle_sun_subgroup_matrix.argtypes = [P, P, I, I, L, I, I, D, P]
+        lib.oracle_sun_apply.argtypes = [P, P, I, L, P]
+        lib.oracle_sun_subgroup_update.argtypes = [P, P, I, I, L, I, I, D]
+        lib.oracle_sun_site_update.argtypes = [P, P, I, I, L, D]
+        lib.oracle_sun_half_sweep.argtypes = [P, P, I, I, I, D]
+        lib.oracle_sun_sweep.argtypes = [P, P, I, I, D]
+        lib.oracle_sun_reunit.argtypes = [P, I, L]
+        lib.oracle_sun_det.argtypes = [P, I, L, P]
+        lib.oracle_sun_fix.argtypes = [P, P, I, I, D, D, I, I, I, L, P, P, P]
+        lib.oracle_sun_fix.restype = I
         _lib = lib
     return _lib
 

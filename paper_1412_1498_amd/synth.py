@@ -42,6 +42,9 @@ __all__ = [
     "random_gauge_field",
     "random_gauge_transform",
     "random_algebra_field",
+    "sun_generators",
+    "haar_sun",
+    "random_sun_field",
 ]
 
 
@@ -73,7 +76,7 @@ def haar_su3(rows: torch.Tensor) -> torch.Tensor:
 
 
 def su3_expi(H: torch.Tensor) -> torch.Tensor:
-    """exp(i H) for Hermitian H (..., 3, 3) by scaling and squaring of a
+    """exp(i H) for Hermitian H (..., n, n) by scaling and squaring of a
     degree-18 Taylor polynomial (every scaled argument has norm <= 1/2)."""
     X = 1j * H
     if X.numel() == 0:
@@ -81,7 +84,7 @@ def su3_expi(H: torch.Tensor) -> torch.Tensor:
     norm = torch.linalg.matrix_norm(X, ord="fro").max().item()
     s = max(0, int(np.ceil(np.log2(max(norm, 1e-300) / 0.5))))
     Y = X / (2.0 ** s)
-    eye = torch.eye(3, dtype=X.dtype, device=X.device).expand_as(X)
+    eye = torch.eye(X.shape[-1], dtype=X.dtype, device=X.device).expand_as(X)
     E = eye.clone()
     for k in range(18, 0, -1):  # Horner: I + Y/1 (I + Y/2 (I + ...))
         E = eye + torch.matmul(Y, E) / k
@@ -153,3 +156,77 @@ def ensemble_members(n_landau: int = 64, seed: int = 0, amp: float = 0.6):
     sides = rng.choice([8, 12, 16, 20, 24], size=n_landau)
     return [((48, 48, 48, 96), 1, amp, 0)] + \
            [((int(L),) * 4, 0, amp, 1 + i) for i, L in enumerate(sides)]
+
+
+# ---- SU(N), N != 3 ----------------------------------------------------------
+
+
+def sun_generators(n: int, dtype=torch.complex128, device="cpu") -> torch.Tensor:
+    """Generalised Gell-Mann matrices of SU(n), shape (n*n - 1, n, n), with
+    Tr T_a T_b = 2 delta_ab: for j < k the symmetric E_jk + E_kj and the
+    antisymmetric -i E_jk + i E_kj, then for l = 1..n-1 the diagonal
+    sqrt(2 / (l (l + 1))) diag(1, ..., 1, -l, 0, ..., 0) (l ones)."""
+    m = []
+    for j in range(n):
+        for k in range(j + 1, n):
+            a = np.zeros((n, n), dtype=np.complex128)
+            a[j, k] = a[k, j] = 1
+            m.append(a)
+            b = np.zeros((n, n), dtype=np.complex128)
+            b[j, k], b[k, j] = -1j, 1j
+            m.append(b)
+    for l in range(1, n):
+        c = np.zeros((n, n), dtype=np.complex128)
+        c[range(l), range(l)] = 1
+        c[l, l] = -l
+        m.append(c * np.sqrt(2.0 / (l * (l + 1))))
+    return torch.from_numpy(np.stack(m)).to(device=device, dtype=dtype)
+
+
+def haar_sun(rows: torch.Tensor) -> torch.Tensor:
+    """Map Ginibre rows (..., n-1, n) complex to Haar SU(n) matrices
+    (..., n, n): Gram-Schmidt of the n-1 rows, last row the complex
+    conjugate of its cofactors (det = 1). For n = 3 this is haar_su3."""
+    n = rows.shape[-1]
+    out = []
+    for r in range(n - 1):
+        v = rows[..., r, :]
+        for q in out:
+            v = v - (q.conj() * v).sum(-1, keepdim=True) * q
+        out.append(v / torch.linalg.vector_norm(v, dim=-1, keepdim=True))
+    top = torch.stack(out, dim=-2)  # (..., n-1, n)
+    last = []
+    for j in range(n):
+        sub = torch.cat([top[..., :, :j], top[..., :, j + 1:]], dim=-1)
+        c = torch.linalg.det(sub)
+        last.append((-c if (n - 1 + j) % 2 else c).conj())
+    return torch.cat([top, torch.stack(last, dim=-1).unsqueeze(-2)], dim=-2)
+
+
+def random_sun_field(dims, n: int, amp: float, seed: int, device="cpu",
+                     chunk_sites: int = 1 << 16) -> torch.Tensor:
+    """Seeded synthetic SU(n) link field, the SU(3) recipe with n colours:
+    U_mu(x) = h(x) exp(i amp sum_a r_a T_a / 2) h(x + mu)^dagger, h Haar on
+    SU(n) (Ginibre rows (V, n-1, n) as (re, im) pairs drawn first, in site
+    order), r ~ N(0, 1) with shape [t][z][y][x][mu][a], a < n*n - 1.
+    Returns complex128, shape (nt, nz, ny, nx, 4, n, n)."""
+    nx, ny, nz, nt = (int(d) for d in dims)
+    V = nx * ny * nz * nt
+    rng = np.random.Generator(np.random.PCG64(seed))
+    g = torch.from_numpy(rng.standard_normal((V, n - 1, n, 2))).to(device)
+    h = haar_sun(torch.complex(g[..., 0], g[..., 1])).reshape(nt, nz, ny, nx, n, n)
+    na = n * n - 1
+    r = rng.standard_normal((V, 4, na))
+    T = sun_generators(n, device=device).reshape(na, n * n)
+    hflat = h.reshape(V, n, n)
+    hfwd = [_shift_fwd(h, mu).reshape(V, n, n) for mu in range(4)]
+    U = torch.empty((V, 4, n, n), dtype=torch.complex128, device=device)
+    for s0 in range(0, V, chunk_sites):
+        s1 = min(V, s0 + chunk_sites)
+        rc = torch.from_numpy(r[s0:s1]).to(device=device, dtype=torch.complex128)
+        H = (0.5 * amp) * torch.matmul(rc, T).reshape(s1 - s0, 4, n, n)
+        E = su3_expi(H)
+        for mu in range(4):
+            U[s0:s1, mu] = torch.matmul(torch.matmul(hflat[s0:s1], E[:, mu]),
+                                        hfwd[mu][s0:s1].transpose(-1, -2).conj())
+    return U.reshape(nt, nz, ny, nx, 4, n, n)
