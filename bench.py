@@ -140,6 +140,57 @@ def run_ensemble(args, gf, synth, torch, np):
     return out
 
 
+def run_sun(args, dims, gf, synth, torch):
+    """SU(N) line (N = 2, 4; all N(N-1)/2 SU(2) subgroups per site): the
+    half-sweep at the main lattice size in FP32 and FP64 (default schedule,
+    amp 0.7, seed 0; 2 warm-up and 10 timed sweeps, HIP events per launch),
+    and Alg. 1 to theta < 1e-7 at 24^4 in FP32 and FP64 (amp 0.5, seed 1,
+    check and reunitarisation every 10 sweeps)."""
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    res = {}
+    for n in (2, 4):
+        log(f"SU({n}) half-sweeps at {'x'.join(map(str, dims))}")
+        U64 = synth.random_sun_field(dims, n, 0.7, 0, device="cuda")
+        for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
+            ctx = gf.Context(dims, prec=prec, nc=n, params=gf.default_params(prec, timing=1))
+            U = ctx.pack(U64.to(ctx.cdtype))
+            ctx.sweeps(U, args.omega, 2)
+            ctx.timing()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.sweeps(U, args.omega, 10)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            ms, nl = ctx.timing()
+            avg = ms / 1e3 / nl
+            per_launch = 16 * n * n * (8 if prec == gf.F32 else 16) * (V // 2)
+            res[f"su{n}_{name}"] = dict(site_sweeps_per_s=V * 10 / wall, avg_launch_us=avg * 1e6,
+                                        algorithmic_bytes_per_launch=per_launch,
+                                        achieved_gbs=per_launch / avg / 1e9,
+                                        frac=per_launch / avg / 1e9 / PEAK_HBM_GBS, schedule=ctx.schedule())
+            del U, ctx
+        del U64
+        torch.cuda.empty_cache()
+        cd = (24, 24, 24, 24)
+        Uc = synth.random_sun_field(cd, n, 0.5, 1, device="cuda")
+        conv = {}
+        for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
+            ctx = gf.Context(cd, prec=prec, nc=n, params=gf.default_params(prec, check_every=10, reunit_every=10))
+            U = ctx.pack(Uc.to(ctx.cdtype))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = ctx.fix(U, args.omega, 1e-7, 20000)
+            torch.cuda.synchronize()
+            conv[name] = dict(seconds=time.perf_counter() - t0, sweeps=r["iters"], converged=r["converged"],
+                              F=r["F"], theta=r["theta"])
+            del U, ctx
+        conv["abs_F_fp32_minus_fp64"] = abs(conv["fp32"]["F"] - conv["fp64"]["F"])
+        res[f"su{n}_24x4_to_theta_1e-7"] = conv
+        del Uc
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,8 +210,10 @@ def main():
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation timing leg")
-    ap.add_argument("--workload", choices=["single", "ensemble"], default="single",
-                    help="ensemble: Coulomb 48^3x96 plus 64 Landau lattices of uneven volume fixed together")
+    ap.add_argument("--no-sun", action="store_true", help="skip the SU(2) / SU(4) leg")
+    ap.add_argument("--workload", choices=["single", "ensemble", "sun"], default="single",
+                    help="ensemble: Coulomb 48^3x96 plus 64 Landau lattices of uneven volume fixed together; "
+                         "sun: only the SU(2) / SU(4) leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch one plain 1 GiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -180,6 +233,10 @@ def main():
         return
 
     dims = tuple(int(x) for x in args.dims.split(","))
+    if args.workload == "sun":
+        print(json.dumps({"workload": "SU(2) and SU(4) overrelaxation, Landau gauge",
+                          "sun": run_sun(args, dims, gf, synth, torch)}), flush=True)
+        return
     V = dims[0] * dims[1] * dims[2] * dims[3]
     spp = args.sweeps_per_step
     storage = gf.STORE_12 if args.storage == 12 else gf.STORE_18
@@ -373,6 +430,9 @@ def main():
         out["differentiation_24x4"] = diffres
         del Ud
         torch.cuda.empty_cache()
+
+    if not args.no_sun:
+        out["sun"] = run_sun(args, dims, gf, synth, torch)
 
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")

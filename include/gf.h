@@ -40,8 +40,17 @@
  *   nb = ceil(V / 128) blocks per parity and ne = 9 (18-real storage) or 6
  *   (12-real storage, gf_params.storage = GF_STORE_12: rows 0 and 1 only, row
  *   2 rebuilt as conj(row0 x row1)). The last block of a parity is padded.
+ * - SU(N): a single-lattice context may also hold N = 2 or 4 colours (the
+ *   paper's method for general N: all N(N-1)/2 SU(2) subgroups (a, b), a < b,
+ *   in lexicographic order). Its links are full N x N matrices in the same
+ *   layout with ne = N * N and e = N row + col; reunitarisation is
+ *   Gram-Schmidt of rows 0..N-2 with the last row the complex conjugate of
+ *   its cofactors; Delta(x) subtracts Tr A / N and F, theta are normalised by
+ *   N. The su(3)-algebra entry points (gf_pack_alg, gf_unpack_alg,
+ *   gf_functional, gf_functional_grad, gf_gauge_transform, gf_sd_step,
+ *   gf_sd_fix) return GF_EUNSUPPORTED for N != 3; ensembles are SU(3).
  * - Canonical layout (pack/unpack only): [t][z][y][x][mu][row][col] complex
- *   in the context's precision.
+ *   in the context's precision (N x N per link).
  * - All work is enqueued on the context's HIP stream (the stream handle passed
  *   at creation; NULL = the default stream). Functions that return results to
  *   the host synchronise that stream; the others are asynchronous.
@@ -64,7 +73,7 @@ extern "C" {
 #define GF_ENOMEM (-2)      /* device or pinned host allocation failed */
 #define GF_EDEVICE (-3)     /* a HIP call failed; gf_last_error() has its message */
 #define GF_ENONFINITE (-4)  /* F or theta came out NaN or infinite */
-#define GF_EUNSUPPORTED (-5)/* e.g. nc != 3 */
+#define GF_EUNSUPPORTED (-5)/* e.g. nc not in {2, 3, 4}; an SU(3)-only call on another N */
 
 enum gf_gauge { GF_LANDAU = 0, GF_COULOMB = 1 };
 enum gf_prec { GF_F64 = 0, GF_F32 = 1 };
@@ -83,10 +92,12 @@ typedef struct gf_params {
     long long start_sweep;  /* global index of the last sweep already done
                                (sets the reunitarisation phase on resume) */
     int storage;            /* GF_STORE_18 (default) or GF_STORE_12 */
-    int lanes_per_site;     /* 0 = default (1), else 1, 2, 4 or 8 lanes per site */
+    int lanes_per_site;     /* 0 = default (1; 2 for SU(4) and double SU(2)),
+                               else 1, 2, 4 or 8 lanes per site (SU(4): >= 2) */
     int block_threads;      /* 0 = default, else 64, 128, 192 or 256 */
     int nontemporal;        /* 1 = streaming (non-temporal) link loads/stores,
-                               0 = plain, -1 = default for the precision */
+                               0 = plain, -1 = default for the precision
+                               (SU(2)/SU(4) kernels always stream) */
     int use_graph;          /* 1 = replay each check period as a hipGraph */
     int timing;             /* 1 = time every half-sweep with hipEvents */
 } gf_params;
@@ -94,12 +105,14 @@ typedef struct gf_params {
 /* Fill *p with the defaults for precision prec. */
 void gf_params_default(gf_params *p, int prec);
 
-/* Create a context for one lattice. dims = {nx, ny, nz, nt}; nc must be 3;
- * gauge is GF_LANDAU or GF_COULOMB; prec is GF_F64 or GF_F32; stream is a
- * hipStream_t (NULL = default stream); p may be NULL for defaults.
- * Returns GF_EINVAL for odd or non-positive dims or a bad enum,
- * GF_EUNSUPPORTED for nc != 3, GF_ENOMEM / GF_EDEVICE on allocation failure
- * (then *out is NULL). On success the context owns its reduction scratch. */
+/* Create a context for one lattice. dims = {nx, ny, nz, nt}; nc is the
+ * number of colours, 3, or 2 or 4 (SU(N) section above); gauge is GF_LANDAU
+ * or GF_COULOMB; prec is GF_F64 or GF_F32; stream is a hipStream_t (NULL =
+ * default stream); p may be NULL for defaults.
+ * Returns GF_EINVAL for odd or non-positive dims, a bad enum or schedule,
+ * GF_EUNSUPPORTED for nc not in {2, 3, 4} or 12-real storage with nc != 3,
+ * GF_ENOMEM / GF_EDEVICE on allocation failure (then *out is NULL). On
+ * success the context owns its reduction scratch. */
 int gf_create(gf_ctx **out, const int dims[4], int nc, int gauge, int prec, void *stream,
               const gf_params *p);
 

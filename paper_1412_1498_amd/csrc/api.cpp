@@ -19,12 +19,14 @@
 #include "gf.h"
 #include "gf_internal.hpp"
 #include "gf_math.hpp"
+#include "sun_internal.hpp"
 
 using namespace gf;
 
 struct gf_ctx {
     int n = 0;
     int prec = 0;
+    int nc = 3;                      // colours: 3, or 2 / 4 (SU(N) kernels)
     int nelem = 9;
     int device = 0;
     hipStream_t stream = nullptr;
@@ -132,19 +134,21 @@ int check_omega(gf_ctx *ctx, double omega) {
 
 // Defaults from the schedule sweep at 48^4 on MI355X (blocked layout): one
 // lane per site with non-temporal link traffic; 128-thread workgroups, 256
-// for 12-real float storage.
-Schedule default_schedule(int prec, const gf_params &p) {
+// for 12-real float storage. SU(4) links need LPS >= 2 (registers); the
+// SU(N) sweep at 48^4 is fastest with LPS 2 for SU(4) and for double SU(2).
+Schedule default_schedule(int prec, int nc, const gf_params &p) {
     Schedule s;
-    s.lps = p.lanes_per_site > 0 ? p.lanes_per_site : 1;
+    s.lps = p.lanes_per_site > 0 ? p.lanes_per_site : ((nc == 4 || (nc == 2 && prec == GF_F64)) ? 2 : 1);
     s.block = p.block_threads > 0 ? p.block_threads
                                    : ((prec == GF_F32 && p.storage == GF_STORE_12) ? 256 : 128);
     s.nt = p.nontemporal >= 0 ? p.nontemporal : 1;
     return s;
 }
 
-int check_schedule(gf_ctx *ctx, const Schedule &s) {
+int check_schedule(gf_ctx *ctx, const Schedule &s, int nc) {
     CHECK(ctx, s.lps == 1 || s.lps == 2 || s.lps == 4 || s.lps == 8, GF_EINVAL,
           "lanes_per_site = %d must be 1, 2, 4 or 8", s.lps);
+    CHECK(ctx, nc != 4 || s.lps >= 2, GF_EINVAL, "SU(4) links need lanes_per_site >= 2");
     CHECK(ctx, s.block >= 64 && s.block <= 256 && s.block % 64 == 0, GF_EINVAL,
           "block_threads = %d must be 64, 128, 192 or 256", s.block);
     return GF_OK;
@@ -216,8 +220,12 @@ int half_sweep(gf_ctx *ctx, int parity, int reunit, const int *d_active) {
         }
         HIPTRY(ctx, hipEventRecord(ev.first, ctx->stream));
     }
-    HIPTRY(ctx, launch_half_sweep(ctx->prec, ctx->nelem, ctx->sched, ctx->d_desc, ctx->d_tile_cfg,
-                                  d_active, ctx->ntiles, parity, reunit, ctx->stream));
+    if (ctx->nc == 3)
+        HIPTRY(ctx, launch_half_sweep(ctx->prec, ctx->nelem, ctx->sched, ctx->d_desc, ctx->d_tile_cfg,
+                                      d_active, ctx->ntiles, parity, reunit, ctx->stream));
+    else
+        HIPTRY(ctx, launch_sun_half_sweep(ctx->prec, ctx->nc, ctx->sched, ctx->d_desc, ctx->d_tile_cfg,
+                                          d_active, ctx->ntiles, parity, reunit, ctx->stream));
     if (ctx->p.timing) {
         HIPTRY(ctx, hipEventRecord(ev.second, ctx->stream));
         ctx->ev_busy.push_back(ev);
@@ -245,11 +253,15 @@ int full_sweeps(gf_ctx *ctx, int n, const int *d_active, hipStream_t st) {
 }
 
 int quality_launch(gf_ctx *ctx, const int *d_active, int update, int swept, double eps, hipStream_t st) {
-    HIPTRY(ctx, launch_quality(ctx->prec, ctx->nelem, ctx->d_desc, ctx->d_qtile_cfg, d_active,
-                               ctx->nqtiles, ctx->d_partials, st));
-    HIPTRY(ctx, launch_quality_final(ctx->d_desc, ctx->n, ctx->d_partials, ctx->d_result,
-                                     update ? ctx->d_active : nullptr, ctx->d_iters, swept, eps,
-                                     update, st));
+    if (ctx->nc == 3)
+        HIPTRY(ctx, launch_quality(ctx->prec, ctx->nelem, ctx->d_desc, ctx->d_qtile_cfg, d_active,
+                                   ctx->nqtiles, ctx->d_partials, st));
+    else
+        HIPTRY(ctx, launch_sun_quality(ctx->prec, ctx->nc, ctx->d_desc, ctx->d_qtile_cfg, d_active,
+                                       ctx->nqtiles, ctx->d_partials, st));
+    HIPTRY(ctx, launch_quality_final_nc(ctx->nc, ctx->d_desc, ctx->n, ctx->d_partials, ctx->d_result,
+                                        update ? ctx->d_active : nullptr, ctx->d_iters, swept, eps,
+                                        update, st));
     return GF_OK;
 }
 
@@ -268,7 +280,7 @@ int read_back(gf_ctx *ctx, bool flags) {
 }
 
 int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec, void *stream,
-                const gf_params *pp) {
+                const gf_params *pp, int nc) {
     if (!out) return GF_EINVAL;
     *out = nullptr;
     gf_ctx tmp;  // for error messages during validation
@@ -284,13 +296,15 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
     if (p.check_every < 1) p.check_every = 1;
     if (p.reunit_every < 0) return GF_EINVAL;
     if (p.storage != GF_STORE_18 && p.storage != GF_STORE_12) return GF_EINVAL;
-    Schedule s = default_schedule(prec, p);
-    if (check_schedule(&tmp, s) != GF_OK) return GF_EINVAL;
+    if (nc != 3 && p.storage != GF_STORE_18) return GF_EUNSUPPORTED;  // 12-real is SU(3) only
+    Schedule s = default_schedule(prec, nc, p);
+    if (check_schedule(&tmp, s, nc) != GF_OK) return GF_EINVAL;
 
     gf_ctx *ctx = new gf_ctx();
     ctx->n = n;
     ctx->prec = prec;
-    ctx->nelem = p.storage == GF_STORE_12 ? 6 : 9;
+    ctx->nc = nc;
+    ctx->nelem = nc != 3 ? nc * nc : (p.storage == GF_STORE_12 ? 6 : 9);
     ctx->stream = (hipStream_t)stream;
     ctx->p = p;
     ctx->sched = s;
@@ -344,6 +358,13 @@ int need_single(gf_ctx *ctx) {
     return GF_OK;
 }
 
+// The su(3)-algebra entry points (differentiation, Fourier-accelerated
+// steepest descent) exist for N = 3 only.
+int need_su3(gf_ctx *ctx) {
+    CHECK(ctx, ctx->nc == 3, GF_EUNSUPPORTED, "this entry point is implemented for SU(3) only (nc = %d)", ctx->nc);
+    return GF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -362,8 +383,8 @@ int gf_create(gf_ctx **out, const int dims[4], int nc, int gauge, int prec, void
               const gf_params *p) {
     if (!out) return GF_EINVAL;
     *out = nullptr;
-    if (nc != 3) return GF_EUNSUPPORTED;
-    return create_impl(out, 1, dims, &gauge, prec, stream, p);
+    if (nc != 2 && nc != 3 && nc != 4) return GF_EUNSUPPORTED;
+    return create_impl(out, 1, dims, &gauge, prec, stream, p, nc);
 }
 
 int gf_batch_create(gf_ctx **out, int n, const int *dims, const int *gauge, int prec, void *stream,
@@ -371,7 +392,7 @@ int gf_batch_create(gf_ctx **out, int n, const int *dims, const int *gauge, int 
     if (!out) return GF_EINVAL;
     *out = nullptr;
     if (n < 1 || !dims || !gauge) return GF_EINVAL;
-    return create_impl(out, n, dims, gauge, prec, stream, p);
+    return create_impl(out, n, dims, gauge, prec, stream, p, 3);
 }
 
 int gf_destroy(gf_ctx *ctx) {
@@ -419,7 +440,10 @@ int gf_pack(gf_ctx *ctx, const void *U_aos, void *U) {
     if ((rc = need_single(ctx)) || (rc = check_field(ctx, U_aos, "U_aos")) || (rc = check_field(ctx, U, "U")))
         return rc;
     DeviceGuard dg(ctx->device);
-    HIPTRY(ctx, launch_pack(ctx->prec, ctx->nelem, ctx->desc[0].g, U_aos, U, 0, ctx->stream));
+    if (ctx->nc == 3)
+        HIPTRY(ctx, launch_pack(ctx->prec, ctx->nelem, ctx->desc[0].g, U_aos, U, 0, ctx->stream));
+    else
+        HIPTRY(ctx, launch_sun_pack(ctx->prec, ctx->nc, ctx->desc[0].g, U_aos, U, 0, ctx->stream));
     return GF_OK;
 }
 
@@ -429,8 +453,12 @@ int gf_unpack(gf_ctx *ctx, const void *U, void *U_aos) {
     if ((rc = need_single(ctx)) || (rc = check_field(ctx, U_aos, "U_aos")) || (rc = check_field(ctx, U, "U")))
         return rc;
     DeviceGuard dg(ctx->device);
-    HIPTRY(ctx, launch_pack(ctx->prec, ctx->nelem, ctx->desc[0].g, U_aos, const_cast<void *>(U), 1,
-                            ctx->stream));
+    if (ctx->nc == 3)
+        HIPTRY(ctx, launch_pack(ctx->prec, ctx->nelem, ctx->desc[0].g, U_aos, const_cast<void *>(U), 1,
+                                ctx->stream));
+    else
+        HIPTRY(ctx, launch_sun_pack(ctx->prec, ctx->nc, ctx->desc[0].g, U_aos, const_cast<void *>(U), 1,
+                                    ctx->stream));
     return GF_OK;
 }
 
@@ -461,7 +489,10 @@ int gf_reunit(gf_ctx *ctx, void *U) {
     int rc;
     if ((rc = need_single(ctx)) || (rc = check_field(ctx, U, "U"))) return rc;
     DeviceGuard dg(ctx->device);
-    HIPTRY(ctx, launch_reunit(ctx->prec, ctx->nelem, ctx->desc[0].g, U, ctx->stream));
+    if (ctx->nc == 3)
+        HIPTRY(ctx, launch_reunit(ctx->prec, ctx->nelem, ctx->desc[0].g, U, ctx->stream));
+    else
+        HIPTRY(ctx, launch_sun_reunit(ctx->prec, ctx->nc, ctx->desc[0].g, U, ctx->stream));
     return GF_OK;
 }
 
@@ -634,7 +665,7 @@ int gf_autotune(gf_ctx *ctx, void *const *U, double omega, const char *cache_pat
         if (!found.empty()) {
             Schedule s{};
             std::istringstream is(found);
-            if (is >> s.lps >> s.block >> s.nt && check_schedule(ctx, s) == GF_OK) {
+            if (is >> s.lps >> s.block >> s.nt && check_schedule(ctx, s, ctx->nc) == GF_OK) {
                 ctx->sched = s;
                 return build_tiles(ctx);
             }
@@ -677,6 +708,8 @@ int gf_autotune(gf_ctx *ctx, void *const *U, double omega, const char *cache_pat
         for (int bi = 0; bi < 3 && rc == GF_OK; bi++)
                 for (int nt = 0; nt < 2 && rc == GF_OK; nt++) {
                     Schedule s{lps_list[li], block_list[bi], nt};
+                    if (ctx->nc == 4 && s.lps < 2) continue;       // registers
+                    if (ctx->nc != 3 && nt != 1) continue;         // SU(N) links are always non-temporal
                     ctx->sched = s;
                     if ((rc = build_tiles(ctx))) break;
                     for (int w = 0; w < 2 && rc == GF_OK; w++) rc = half_sweep(ctx, w & 1, 0, ctx->d_ones);
@@ -725,7 +758,8 @@ int ensure_diff_scratch(gf_ctx *ctx) {
 
 int diff_prologue(gf_ctx *ctx, const void *U, const void *s) {
     int rc;
-    if ((rc = need_single(ctx)) || (rc = check_field(ctx, U, "U")) || (rc = check_field(ctx, s, "s")))
+    if ((rc = need_single(ctx)) || (rc = need_su3(ctx)) || (rc = check_field(ctx, U, "U")) ||
+        (rc = check_field(ctx, s, "s")))
         return rc;
     if ((rc = ensure_diff_scratch(ctx))) return rc;
     HIPTRY(ctx, launch_expS(ctx->prec, ctx->desc[0].g, s, ctx->d_gfield, ctx->stream));
@@ -737,7 +771,8 @@ int diff_prologue(gf_ctx *ctx, const void *U, const void *s) {
 int gf_pack_alg(gf_ctx *ctx, const void *s_aos, void *s) {
     if (!ctx) return GF_EINVAL;
     int rc;
-    if ((rc = need_single(ctx)) || (rc = check_field(ctx, s_aos, "s_aos")) || (rc = check_field(ctx, s, "s")))
+    if ((rc = need_single(ctx)) || (rc = need_su3(ctx)) || (rc = check_field(ctx, s_aos, "s_aos")) ||
+        (rc = check_field(ctx, s, "s")))
         return rc;
     DeviceGuard dg(ctx->device);
     HIPTRY(ctx, launch_pack_alg(ctx->prec, ctx->desc[0].g, s_aos, s, 0, ctx->stream));
@@ -747,7 +782,8 @@ int gf_pack_alg(gf_ctx *ctx, const void *s_aos, void *s) {
 int gf_unpack_alg(gf_ctx *ctx, const void *s, void *s_aos) {
     if (!ctx) return GF_EINVAL;
     int rc;
-    if ((rc = need_single(ctx)) || (rc = check_field(ctx, s_aos, "s_aos")) || (rc = check_field(ctx, s, "s")))
+    if ((rc = need_single(ctx)) || (rc = need_su3(ctx)) || (rc = check_field(ctx, s_aos, "s_aos")) ||
+        (rc = check_field(ctx, s, "s")))
         return rc;
     DeviceGuard dg(ctx->device);
     HIPTRY(ctx, launch_pack_alg(ctx->prec, ctx->desc[0].g, s_aos, const_cast<void *>(s), 1, ctx->stream));
@@ -885,7 +921,9 @@ int check_alpha(gf_ctx *ctx, double alpha) {
 int gf_sd_step(gf_ctx *ctx, void *U, double alpha) {
     if (!ctx) return GF_EINVAL;
     int rc;
-    if ((rc = need_single(ctx)) || (rc = check_field(ctx, U, "U")) || (rc = check_alpha(ctx, alpha))) return rc;
+    if ((rc = need_single(ctx)) || (rc = need_su3(ctx)) || (rc = check_field(ctx, U, "U")) ||
+        (rc = check_alpha(ctx, alpha)))
+        return rc;
     DeviceGuard dg(ctx->device);
     if ((rc = sd_prepare(ctx))) return rc;
     return sd_step_impl(ctx, U, alpha);
@@ -895,7 +933,9 @@ int gf_sd_fix(gf_ctx *ctx, void *U, double alpha, double eps, int max_iter, int 
               double *theta) {
     if (!ctx) return GF_EINVAL;
     int rc;
-    if ((rc = need_single(ctx)) || (rc = check_field(ctx, U, "U")) || (rc = check_alpha(ctx, alpha))) return rc;
+    if ((rc = need_single(ctx)) || (rc = need_su3(ctx)) || (rc = check_field(ctx, U, "U")) ||
+        (rc = check_alpha(ctx, alpha)))
+        return rc;
     CHECK(ctx, iters && F && theta, GF_EINVAL, "NULL argument");
     CHECK(ctx, std::isfinite(eps) && eps >= 0.0, GF_EINVAL, "eps must be finite and >= 0");
     CHECK(ctx, max_iter >= 0, GF_EINVAL, "max_iter must be >= 0");

@@ -17,6 +17,8 @@
 // normalises. Neither stage
 // depends on the sweep schedule, so F and theta are bitwise reproducible.
 #include "su3_device.hpp"
+#include "sun_device.hpp"
+#include "sun_internal.hpp"
 
 namespace gf {
 
@@ -116,7 +118,7 @@ constexpr int QFINAL = 1024;
 __global__ void __launch_bounds__(QFINAL)
 k_quality_final(const CfgDesc *__restrict__ desc, const double *__restrict__ partials,
                 double *__restrict__ result, int *__restrict__ active, int *__restrict__ iters,
-                int swept, double eps, int update_active) {
+                int swept, double eps, int update_active, double ncol) {
     const int c = blockIdx.x;
     if (update_active && !active[c]) return;
     const CfgDesc d = desc[c];
@@ -131,8 +133,8 @@ k_quality_final(const CfgDesc *__restrict__ desc, const double *__restrict__ par
     block_sum2(fs, ts);
     if (threadIdx.x == 0) {
         const int nd = d.gauge == 0 ? 4 : 3;
-        const double F = fs / (nd * 3.0 * (double)d.g.V);
-        const double th = ts / (3.0 * (double)d.g.V);
+        const double F = fs / (nd * ncol * (double)d.g.V);
+        const double th = ts / (ncol * (double)d.g.V);
         result[2 * c] = F;
         result[2 * c + 1] = th;
         if (update_active) {
@@ -163,8 +165,87 @@ hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int 
 hipError_t launch_quality_final(const CfgDesc *d_desc, int n, const double *d_partials,
                                 double *d_result, int *d_active, int *d_iters, int swept,
                                 double eps, int update_active, hipStream_t st) {
+    return launch_quality_final_nc(3, d_desc, n, d_partials, d_result, d_active, d_iters, swept, eps,
+                                   update_active, st);
+}
+
+hipError_t launch_quality_final_nc(int nc, const CfgDesc *d_desc, int n, const double *d_partials,
+                                   double *d_result, int *d_active, int *d_iters, int swept, double eps,
+                                   int update_active, hipStream_t st) {
     hipLaunchKernelGGL(k_quality_final, dim3(n), dim3(QFINAL), 0, st, d_desc, d_partials, d_result,
-                       d_active, d_iters, swept, eps, update_active);
+                       d_active, d_iters, swept, eps, update_active, (double)nc);
+    return hipGetLastError();
+}
+
+// SU(N): the same tiles and reductions, N x N links, trace / N in Delta.
+template <typename R, int N>
+__global__ void __launch_bounds__(QTILE)
+k_sun_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
+              const int *__restrict__ active, double *__restrict__ partials) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int c = qtile_cfg[tile];
+    if (active && !active[c]) return;
+    const CfgDesc d = desc[c];
+    const Geom &g = d.g;
+    constexpr int QH = QTILE / 2;
+    constexpr int E = N * N;
+    const int p = threadIdx.x >= QH;
+    const int h = (tile - d.qtile0) * QH + (int)threadIdx.x - p * QH;
+    const int nd = d.gauge == 0 ? 4 : 3;
+    double fsum = 0.0, tsum = 0.0;
+    if (h < g.Vh) {
+        const SiteNbr nb = site_neighbours(g, p, h);
+        const gchar *U = as_global(d.U);
+        double mr[E], mi[E];
+#pragma unroll
+        for (int e = 0; e < E; e++) { mr[e] = 0.0; mi[e] = 0.0; }
+        for (int mu = 0; mu < nd; mu++) {
+            MatN<R, N> f, b;
+            load_link_n<R, N, false>(f, U, link_off(g, mu, p, h));
+            load_link_n<R, N, false>(b, U, link_off(g, mu, 1 - p, pick4(nb.hb, mu)));
+#pragma unroll
+            for (int r = 0; r < N; r++) fsum += (double)f.re[(N + 1) * r];
+#pragma unroll
+            for (int e = 0; e < E; e++) {
+                mr[e] += (double)b.re[e] - (double)f.re[e];
+                mi[e] += (double)b.im[e] - (double)f.im[e];
+            }
+        }
+        double ar[E], ai[E];
+#pragma unroll
+        for (int r = 0; r < N; r++)
+#pragma unroll
+            for (int cc = 0; cc < N; cc++) {
+                ar[N * r + cc] = mr[N * r + cc] - mr[N * cc + r];
+                ai[N * r + cc] = mi[N * r + cc] + mi[N * cc + r];
+            }
+        double trr = 0.0, tri = 0.0;
+#pragma unroll
+        for (int r = 0; r < N; r++) { trr += ar[(N + 1) * r]; tri += ai[(N + 1) * r]; }
+        trr /= (double)N;
+        tri /= (double)N;
+#pragma unroll
+        for (int r = 0; r < N; r++) { ar[(N + 1) * r] -= trr; ai[(N + 1) * r] -= tri; }
+#pragma unroll
+        for (int e = 0; e < E; e++) tsum += ar[e] * ar[e] + ai[e] * ai[e];
+    }
+    block_sum2(fsum, tsum);
+    if (threadIdx.x == 0) {
+        partials[2 * tile] = fsum;
+        partials[2 * tile + 1] = tsum;
+    }
+}
+
+hipError_t launch_sun_quality(int prec, int nc, const CfgDesc *d_desc, const int *d_qtile_cfg,
+                              const int *d_active, int nqtiles, double *d_partials, hipStream_t st) {
+    if (nqtiles <= 0) return hipSuccess;
+#define GF_Q(R, N)                                                                                 \
+    hipLaunchKernelGGL((k_sun_quality<R, N>), dim3(nqtiles), dim3(QTILE), 0, st, d_desc, d_qtile_cfg, \
+                       d_active, d_partials)
+    if (nc == 2) { if (prec == 0) GF_Q(double, 2); else GF_Q(float, 2); }
+    else if (nc == 4) { if (prec == 0) GF_Q(double, 4); else GF_Q(float, 4); }
+    else return hipErrorInvalidValue;
+#undef GF_Q
     return hipGetLastError();
 }
 

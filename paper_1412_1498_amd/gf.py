@@ -136,20 +136,25 @@ class Context:
     """A libgf context: one lattice, or an ensemble of lattices (n > 1)."""
 
     def __init__(self, dims, gauge=LANDAU, prec=F32, stream=None, params: Params | None = None,
-                 ensemble=None):
+                 ensemble=None, nc=3):
+        """nc: number of colours of a single lattice (3, or 2 / 4 for the SU(N)
+        kernels); ensembles are SU(3)."""
         self.prec = prec
+        self.nc = int(nc)
         self.rdtype = torch.float64 if prec == F64 else torch.float32
         self.cdtype = torch.complex128 if prec == F64 else torch.complex64
         p = params if params is not None else default_params(prec)
         self.storage = p.storage
-        self.nelem = 6 if p.storage == STORE_12 else 9
+        self.nelem = (6 if p.storage == STORE_12 else 9) if self.nc == 3 else self.nc * self.nc
         self._h = ctypes.c_void_p()
         sh = _stream_handle(stream)
         if ensemble is None:
             self.members = [(tuple(int(x) for x in dims), int(gauge))]
-            rc = lib.gf_create(ctypes.byref(self._h), _dims_arr(dims), 3, int(gauge), prec, sh,
+            rc = lib.gf_create(ctypes.byref(self._h), _dims_arr(dims), self.nc, int(gauge), prec, sh,
                                ctypes.byref(p))
         else:
+            if self.nc != 3:
+                raise ValueError("ensembles are SU(3) only")
             self.members = [(tuple(int(x) for x in d), int(g)) for d, g in ensemble]
             n = len(self.members)
             dd = (ctypes.c_int * (4 * n))(*[x for d, _ in self.members for x in d])
@@ -210,10 +215,16 @@ class Context:
             raise ValueError(f"field must be {self.rdtype} with {n} elements")
         return _ptr(U)
 
+    def _canonical_shape(self, i=0):
+        d = self.members[i][0]
+        return (d[3], d[2], d[1], d[0], 4, self.nc, self.nc)
+
     def pack(self, U_aos: torch.Tensor, U: torch.Tensor | None = None) -> torch.Tensor:
-        """Canonical complex (nt, nz, ny, nx, 4, 3, 3) -> internal layout."""
+        """Canonical complex (nt, nz, ny, nx, 4, N, N) -> internal layout."""
         if U_aos.dtype != self.cdtype:
             raise ValueError(f"canonical field must be {self.cdtype}")
+        if tuple(U_aos.shape) != self._canonical_shape():
+            raise ValueError(f"canonical field must have shape {self._canonical_shape()}")
         if U is None:
             U = self.empty_field(device=U_aos.device)
         self._check(lib.gf_pack(self._h, ctypes.c_void_p(_ptr(U_aos)),
@@ -221,9 +232,10 @@ class Context:
         return U
 
     def unpack(self, U: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
-        d = self.members[0][0]
         if out is None:
-            out = torch.empty((d[3], d[2], d[1], d[0], 4, 3, 3), dtype=self.cdtype, device=U.device)
+            out = torch.empty(self._canonical_shape(), dtype=self.cdtype, device=U.device)
+        elif tuple(out.shape) != self._canonical_shape() or out.dtype != self.cdtype:
+            raise ValueError(f"out must be {self.cdtype} with shape {self._canonical_shape()}")
         self._check(lib.gf_unpack(self._h, ctypes.c_void_p(self._check_field(U)),
                                   ctypes.c_void_p(_ptr(out))))
         return out

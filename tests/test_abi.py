@@ -39,8 +39,16 @@ def test_invalid_arguments_fail_before_device_use(gf):
     for dims in [(3, 4, 4, 4), (4, 4, 4, 0), (4, 4, 5, 4), (4, -2, 4, 4)]:
         rc = gf.lib.gf_create(ctypes.byref(h), gf._dims_arr(dims), 3, 0, gf.F32, None, ctypes.byref(p))
         assert rc == gf.EINVAL and not h.value
-    assert gf.lib.gf_create(ctypes.byref(h), gf._dims_arr((4, 4, 4, 4)), 2, 0, gf.F32, None,
-                            ctypes.byref(p)) == gf.EUNSUPPORTED
+    for nc in (1, 5, 8):
+        assert gf.lib.gf_create(ctypes.byref(h), gf._dims_arr((4, 4, 4, 4)), nc, 0, gf.F32, None,
+                                ctypes.byref(p)) == gf.EUNSUPPORTED
+    # 12-real storage is SU(3) only; SU(4) links need two or more lanes per site
+    p12 = gf.default_params(gf.F32, storage=gf.STORE_12)
+    assert gf.lib.gf_create(ctypes.byref(h), gf._dims_arr((4, 4, 4, 4)), 4, 0, gf.F32, None,
+                            ctypes.byref(p12)) == gf.EUNSUPPORTED
+    p1 = gf.default_params(gf.F32, lanes_per_site=1)
+    assert gf.lib.gf_create(ctypes.byref(h), gf._dims_arr((4, 4, 4, 4)), 4, 0, gf.F32, None,
+                            ctypes.byref(p1)) == gf.EINVAL
     assert gf.lib.gf_create(ctypes.byref(h), gf._dims_arr((4, 4, 4, 4)), 3, 5, gf.F32, None,
                             ctypes.byref(p)) == gf.EINVAL
     assert gf.lib.gf_create(ctypes.byref(h), gf._dims_arr((4, 4, 4, 4)), 3, 0, 7, None,

@@ -1,0 +1,233 @@
+"""GPU parity of the SU(N) kernels (N = 2, 4) against the SU(N) FP64 oracle,
+through the C ABI. Inputs are seeded synthetic SU(N) fields; FP32 runs give
+the oracle the exact double promotion of the float field.
+
+Tolerances (as for SU(3)): FP64 links after a half-sweep 1e-13 abs; FP32
+links 5e-6 abs (G rounded to float, N products per entry, N(N-1)/2 subgroup
+steps folded into one product in double); theta 1e-13 relative and F 1e-13
+absolute (only the summation order differs; F averages nearly cancelling
+terms in [-1, 1] on these fields)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import sun
+
+pytestmark = pytest.mark.gpu
+
+LANDAU, COULOMB = 0, 1
+LPS = {2: [1, 2, 4, 8], 4: [2, 4, 8]}
+
+
+@pytest.fixture(scope="module")
+def gf():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1412_1498_amd import gf as mod
+    return mod
+
+
+_cache = {}
+
+
+def field(dims, n, amp, seed):
+    from paper_1412_1498_amd import synth
+    key = (dims, n, amp, seed)
+    if key not in _cache:
+        _cache[key] = np.ascontiguousarray(synth.random_sun_field(dims, n, amp, seed).numpy())
+    return _cache[key].copy()
+
+
+def ctx_of(gf, dims, n, gauge, prec, **kw):
+    return gf.Context(dims, gauge=gauge, prec=prec, params=gf.default_params(prec, **kw), nc=n)
+
+
+def to_gpu(ctx, U):
+    return ctx.pack(torch.from_numpy(U).to("cuda", dtype=ctx.cdtype))
+
+
+def to_host(ctx, U):
+    return ctx.unpack(U).cpu().numpy().astype(np.complex128)
+
+
+def promoted(U, prec):
+    return U.astype(np.complex64).astype(np.complex128) if prec == 1 else U.copy()
+
+
+@pytest.mark.parametrize("n", [2, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_pack_roundtrip_and_layout(gf, n, prec):
+    dims = (4, 6, 2, 8)
+    U = field(dims, n, 0.5, 1)
+    ctx = ctx_of(gf, dims, n, LANDAU, prec)
+    Ug = to_gpu(ctx, U)
+    assert Ug.numel() * Ug.element_size() == ctx.field_bytes()
+    back = ctx.unpack(Ug).cpu().numpy()
+    assert np.array_equal(back, U.astype(back.dtype))
+    # element e = N row + col of U_mu at (p, h) sits at the blocked offset
+    raw = Ug.cpu().numpy().reshape(-1, 2)
+    nb = ctx.blocks()
+    V = int(np.prod(dims))
+    for s in (0, 5, 77, V - 1):
+        x, y, z, t = s % 4, (s // 4) % 6, (s // 24) % 2, s // 48
+        p, h = (x + y + z + t) % 2, s // 2
+        for mu in (0, 3):
+            for e in (0, n * n - 1):
+                off = (((p * nb + h // 64) * 4 + mu) * n * n + e) * 64 + h % 64
+                val = raw[off, 0] + 1j * raw[off, 1]
+                assert val == U.reshape(V, 4, n * n)[s, mu, e].astype(back.dtype)
+
+
+@pytest.mark.parametrize("n", [2, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 6, 2, 8), (8, 6, 8, 8)])
+def test_quality_matches_oracle(gf, n, prec, gauge, dims):
+    U = field(dims, n, 0.6, 2)
+    ctx = ctx_of(gf, dims, n, gauge, prec)
+    F, th = ctx.quality(to_gpu(ctx, U))
+    Fo, tho = sun.quality(promoted(U, prec), dims, gauge)
+    # F averages terms in [-1, 1] that nearly cancel on these Haar-rotated
+    # fields (F ~ 1e-5), so its bound is absolute; theta sums positive terms
+    assert abs(F - Fo) <= 1e-13 and abs(th - tho) <= 1e-13 * tho
+
+
+@pytest.mark.parametrize("n", [2, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("dims", [(4, 4, 4, 4), (4, 6, 2, 8)])
+def test_half_sweeps_match_oracle(gf, n, prec, gauge, dims):
+    """Every schedule, four half-sweeps; before each the oracle gets the
+    GPU's current field (promoted), so each half-sweep is compared alone."""
+    U = field(dims, n, 0.7, 3)
+    tol = 1e-13 if prec == 0 else 5e-6
+    for lps in LPS[n]:
+        ctx = ctx_of(gf, dims, n, gauge, prec, lanes_per_site=lps)
+        Ug = to_gpu(ctx, U)
+        cur = promoted(U, prec)
+        for k in range(4):
+            ctx.sweep(Ug, k % 2, 1.7)
+            sun.half_sweep(cur, dims, k % 2, 1.7, gauge)
+            got = to_host(ctx, Ug)
+            assert np.abs(got - cur).max() < tol, (lps, k)
+            cur = got
+
+
+@pytest.mark.parametrize("n", [2, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_all_schedules_give_identical_bits(gf, n, prec):
+    dims = (8, 4, 4, 6)
+    U = field(dims, n, 0.7, 4)
+    ref = None
+    for lps in LPS[n]:
+        for block in (64, 128, 256):
+            ctx = ctx_of(gf, dims, n, LANDAU, prec, lanes_per_site=lps, block_threads=block, reunit_every=2)
+            Ug = to_gpu(ctx, U)
+            ctx.sweeps(Ug, 1.7, 3)
+            if ref is None:
+                ref = Ug.clone()
+            else:
+                assert torch.equal(Ug, ref), (lps, block)
+
+
+@pytest.mark.parametrize("n", [2, 4])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+def test_fix_matches_oracle_fp64(gf, n, gauge):
+    """Alg. 1 to theta < 1e-12 with reunitarisation every 4 sweeps: same
+    sweep count (+-1: theta near the threshold) and F within 1e-12."""
+    dims = (4, 4, 4, 4)
+    U = field(dims, n, 0.3, 5)
+    ctx = ctx_of(gf, dims, n, gauge, 0, reunit_every=4)
+    r = ctx.fix(to_gpu(ctx, U), 1.7, 1e-12, 3000)
+    ro = sun.fix(U.copy(), dims, 1.7, 1e-12, 3000, gauge, reunit_every=4)
+    assert r["converged"] and ro["converged"]
+    assert abs(r["iters"] - ro["iters"]) <= 1 and abs(r["F"] - ro["F"]) < 1e-12
+
+
+@pytest.mark.parametrize("n", [2, 4])
+def test_fix_schedule_check_and_reunit(gf, n):
+    """max_iter not a multiple of check_every or reunit_every: the GPU field
+    after the run equals the oracle's (same schedule), FP64."""
+    dims = (4, 2, 4, 4)
+    U = field(dims, n, 0.6, 6)
+    ctx = ctx_of(gf, dims, n, LANDAU, 0, check_every=3, reunit_every=2)
+    Ug = to_gpu(ctx, U)
+    r = ctx.fix(Ug, 1.7, 0.0, 7)
+    cur = U.copy()
+    ro = sun.fix(cur, dims, 1.7, 0.0, 7, LANDAU, reunit_every=2, check_every=3)
+    assert r["iters"] == ro["iters"] == 7
+    assert np.abs(to_host(ctx, Ug) - cur).max() < 1e-12
+    assert abs(r["theta"] - ro["theta"]) < 1e-12 * ro["theta"]
+
+
+@pytest.mark.parametrize("n", [2, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_reunit_matches_oracle(gf, n, prec):
+    dims = (4, 4, 2, 2)
+    U = field(dims, n, 0.5, 7)
+    P = np.ascontiguousarray(U + 1e-3 * np.random.default_rng(8).standard_normal(U.shape))
+    ctx = ctx_of(gf, dims, n, LANDAU, prec)
+    Ug = to_gpu(ctx, P)
+    ctx.reunit(Ug)
+    ref = promoted(P, prec)
+    sun.reunit(ref)
+    got = to_host(ctx, Ug)
+    assert np.abs(got - ref).max() < (1e-14 if prec == 0 else 3e-7)
+    L = got.reshape(-1, n, n)
+    assert np.abs(np.linalg.det(L) - 1).max() < (1e-14 if prec == 0 else 1e-6)
+
+
+def test_fp32_su4_reaches_target_and_tracks_fp64(gf):
+    dims = (8, 8, 8, 8)
+    U = field(dims, 4, 0.5, 9)
+    c32 = ctx_of(gf, dims, 4, LANDAU, 1, check_every=10, reunit_every=10)
+    r32 = c32.fix(to_gpu(c32, U), 1.7, 1e-7, 5000)
+    ro = sun.fix(U.copy(), dims, 1.7, 1e-7, 5000, LANDAU, reunit_every=10, check_every=10)
+    assert r32["converged"] and ro["converged"]
+    assert abs(r32["F"] - ro["F"]) < 1e-5
+
+
+def test_full_size_su4_sampled_sites(gf):
+    """SU(4), 32^4, FP32, default schedule: F and theta of the whole field
+    equal the oracle's (theta 1e-10 relative: the oracle's sequential sum over
+    ~1e6 positive terms, as for SU(3) at 48^4; F, an average of ~4e6 terms in
+    [-1, 1] that nearly cancel, 1e-11 absolute); after one even half-sweep,
+    sampled sites equal the oracle's single-site update."""
+    from paper_1412_1498_amd import synth
+    dims = (32, 32, 32, 32)
+    n = 4
+    U = synth.random_sun_field(dims, n, 0.6, 10, device="cuda").to(torch.complex64)
+    ctx = ctx_of(gf, dims, n, LANDAU, 1)
+    Ug = ctx.pack(U)
+    F0, th0 = ctx.quality(Ug)
+    Uo = U.cpu().numpy().astype(np.complex128)
+    del U
+    Fo, tho = sun.quality(Uo, dims)
+    assert abs(F0 - Fo) <= 1e-11 and abs(th0 - tho) <= 1e-10 * tho
+    ctx.sweep(Ug, 0, 1.7)
+    back = to_host(ctx, Ug)
+    V = int(np.prod(dims))
+    par = np.indices((32, 32, 32, 32)).sum(0).reshape(-1) % 2  # (t, z, y, x) order, same parity
+    rng = np.random.default_rng(0)
+    sites = [int(s) for s in rng.choice(V, 200, replace=False) if par[s] == 0][:48]
+    for s in sites:
+        sun.site_update(Uo, dims, s, 1.7)
+    B, O = back.reshape(V, 4, n, n), Uo.reshape(V, 4, n, n)
+    for s in sites:
+        np.testing.assert_allclose(B[s], O[s], atol=5e-6)
+        x, y, z, t = s % 32, (s // 32) % 32, (s // 1024) % 32, s // 32768
+        for mu, (c, step) in enumerate(zip((x, y, z, t), (1, 32, 1024, 32768))):
+            b = s - step if c > 0 else s + 31 * step
+            np.testing.assert_allclose(B[b, mu], O[b, mu], atol=5e-6)
+
+
+def test_su3_only_entry_points_are_refused(gf):
+    dims = (4, 4, 4, 4)
+    ctx = ctx_of(gf, dims, 4, LANDAU, 1)
+    Ug = to_gpu(ctx, field(dims, 4, 0.5, 11))
+    with pytest.raises(gf.GFError) as e:
+        ctx.sd_step(Ug, 0.08)
+    assert e.value.code == gf.EUNSUPPORTED
+    s = torch.zeros((8, 2, 128), dtype=torch.float32, device="cuda")
+    with pytest.raises(gf.GFError) as e:
+        ctx.functional(Ug, s)
+    assert e.value.code == gf.EUNSUPPORTED
