@@ -14,6 +14,7 @@
 #include <map>
 #include <sstream>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "gf.h"
@@ -52,8 +53,9 @@ struct gf_ctx {
     std::string err;
     // timing
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_busy, ev_free;
-    // graphs of check periods, keyed by (sweeps, reunit pattern)
-    std::map<std::pair<int, unsigned long long>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // graphs of check periods, keyed by (sweeps, reunit pattern, bits of eps):
+    // eps is a kernel argument of the captured final reduction
+    std::map<std::tuple<int, unsigned long long, unsigned long long>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     hipStream_t cap_stream = nullptr;
     // differentiation scratch: g field (9 complex per site) and partials
     void *d_gfield = nullptr;
@@ -568,7 +570,9 @@ int gf_batch_fix(gf_ctx *ctx, void *const *U, const double *omega, double eps, i
             unsigned long long pattern = 0;
             for (int k = 1; k <= m; k++)
                 if (reunit_due(ctx, ctx->sweeps_done + k)) pattern |= 1ULL << (k - 1);
-            auto key = std::make_pair(m, pattern);
+            unsigned long long eps_bits;
+            std::memcpy(&eps_bits, &eps, sizeof eps_bits);
+            auto key = std::make_tuple(m, pattern, eps_bits);
             auto f = ctx->graphs.find(key);
             if (f == ctx->graphs.end()) {
                 hipGraph_t g;
@@ -745,13 +749,19 @@ namespace {
 
 int ensure_diff_scratch(gf_ctx *ctx) {
     const Geom &g = ctx->desc[0].g;
-    if (!ctx->d_gfield) {
-        if (hipMalloc(&ctx->d_gfield, 9 * (size_t)g.V * csize(ctx)) != hipSuccess)
-            return fail(ctx, GF_ENOMEM, "cannot allocate the g field");
-        const int nb = (g.V + 255) / 256;
-        if (hipMalloc(&ctx->d_fpart, nb * sizeof(double)) != hipSuccess ||
-            hipMalloc(&ctx->d_fout, sizeof(double)) != hipSuccess)
-            return fail(ctx, GF_ENOMEM, "cannot allocate functional partials");
+    // each buffer on its own, so a call after a failed allocation retries it
+    if (!ctx->d_gfield && hipMalloc(&ctx->d_gfield, 9 * (size_t)g.V * csize(ctx)) != hipSuccess) {
+        ctx->d_gfield = nullptr;
+        return fail(ctx, GF_ENOMEM, "cannot allocate the g field");
+    }
+    const int nb = (g.V + 255) / 256;
+    if (!ctx->d_fpart && hipMalloc(&ctx->d_fpart, nb * sizeof(double)) != hipSuccess) {
+        ctx->d_fpart = nullptr;
+        return fail(ctx, GF_ENOMEM, "cannot allocate functional partials");
+    }
+    if (!ctx->d_fout && hipMalloc(&ctx->d_fout, sizeof(double)) != hipSuccess) {
+        ctx->d_fout = nullptr;
+        return fail(ctx, GF_ENOMEM, "cannot allocate the functional result");
     }
     return GF_OK;
 }
@@ -850,22 +860,43 @@ int sd_prepare(gf_ctx *ctx) {
     const Geom &g = ctx->desc[0].g;
     const size_t rs = ctx->prec == GF_F64 ? 8 : 4;
     const long long S = (long long)g.nz * g.ny * (g.nx / 2 + 1);
-    if (hipMalloc(&ctx->d_sd, 8 * (size_t)g.V * rs) != hipSuccess ||
-        hipMalloc(&ctx->d_spec, 8 * (size_t)g.nt * S * 2 * rs) != hipSuccess)
+    // every resource is made only if missing, so a call after a failure
+    // resumes where it stopped instead of leaking what was already made
+    if (!ctx->d_sd && hipMalloc(&ctx->d_sd, 8 * (size_t)g.V * rs) != hipSuccess) {
+        ctx->d_sd = nullptr;
         return fail(ctx, GF_ENOMEM, "cannot allocate the Fourier acceleration buffers");
+    }
+    if (!ctx->d_spec && hipMalloc(&ctx->d_spec, 8 * (size_t)g.nt * S * 2 * rs) != hipSuccess) {
+        ctx->d_spec = nullptr;
+        return fail(ctx, GF_ENOMEM, "cannot allocate the Fourier acceleration buffers");
+    }
     int n3[3] = {g.nz, g.ny, g.nx};
     const bool dp = ctx->prec == GF_F64;
-    FFTTRY(ctx, hipfftPlanMany(&ctx->fft_fwd, 3, n3, nullptr, 1, g.nz * g.ny * g.nx, nullptr, 1, (int)S,
-                               dp ? HIPFFT_D2Z : HIPFFT_R2C, 8 * g.nt));
-    FFTTRY(ctx, hipfftPlanMany(&ctx->fft_inv, 3, n3, nullptr, 1, (int)S, nullptr, 1, g.nz * g.ny * g.nx,
-                               dp ? HIPFFT_Z2D : HIPFFT_C2R, 8 * g.nt));
-    FFTTRY(ctx, hipfftSetStream(ctx->fft_fwd, ctx->stream));
-    FFTTRY(ctx, hipfftSetStream(ctx->fft_inv, ctx->stream));
+    // a plan is kept only once it was made and bound to the stream
+    auto make_plan = [&](hipfftHandle &out, int rank, int *n, int *inembed, int istride, int idist,
+                         int *onembed, int ostride, int odist, hipfftType type, int batch) -> int {
+        if (out) return GF_OK;
+        hipfftHandle h = 0;
+        hipfftResult r = hipfftPlanMany(&h, rank, n, inembed, istride, idist, onembed, ostride, odist, type, batch);
+        if (r == HIPFFT_SUCCESS) r = hipfftSetStream(h, ctx->stream);
+        if (r != HIPFFT_SUCCESS) {
+            if (h) (void)hipfftDestroy(h);
+            return fail(ctx, GF_EDEVICE, "hipfft plan creation failed: hipfft status %d", (int)r);
+        }
+        out = h;
+        return GF_OK;
+    };
+    if ((rc = make_plan(ctx->fft_fwd, 3, n3, nullptr, 1, g.nz * g.ny * g.nx, nullptr, 1, (int)S,
+                        dp ? HIPFFT_D2Z : HIPFFT_R2C, 8 * g.nt)))
+        return rc;
+    if ((rc = make_plan(ctx->fft_inv, 3, n3, nullptr, 1, (int)S, nullptr, 1, g.nz * g.ny * g.nx,
+                        dp ? HIPFFT_Z2D : HIPFFT_C2R, 8 * g.nt)))
+        return rc;
     if (ctx->desc[0].gauge == GF_LANDAU) {
         int nt1[1] = {g.nt};
-        FFTTRY(ctx, hipfftPlanMany(&ctx->fft_t, 1, nt1, nt1, (int)S, 1, nt1, (int)S, 1,
-                                   dp ? HIPFFT_Z2Z : HIPFFT_C2C, (int)S));
-        FFTTRY(ctx, hipfftSetStream(ctx->fft_t, ctx->stream));
+        if ((rc = make_plan(ctx->fft_t, 1, nt1, nt1, (int)S, 1, nt1, (int)S, 1, dp ? HIPFFT_Z2Z : HIPFFT_C2C,
+                            (int)S)))
+            return rc;
     }
     ctx->sd_ready = true;
     return GF_OK;

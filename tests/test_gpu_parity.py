@@ -242,6 +242,25 @@ def test_batch_fix_equals_single_fix(gf, field_cache, use_graph):
         assert torch.equal(singles[i], Us[i])
 
 
+def test_graph_replay_follows_a_new_eps(gf, field_cache):
+    """A context that replayed graphs for one threshold gives, for another
+    threshold, exactly what a fresh context gives (the captured check period
+    must not keep the first eps)."""
+    d, amp, seed = (8, 8, 8, 8), 0.5, 12
+    prec = 1
+    kw = dict(check_every=5, reunit_every=5, use_graph=1)
+    ctx = make_ctx(gf, d, LANDAU, prec, **kw)
+    ctx.fix(to_gpu(ctx, field_cache(d, amp, seed)), 1.7, 1e-2, 3000)
+    ctx.sweep_count = 0
+    U = to_gpu(ctx, field_cache(d, amp, seed))
+    r = ctx.fix(U, 1.7, 1e-8, 3000)
+    fresh = make_ctx(gf, d, LANDAU, prec, **kw)
+    V = to_gpu(fresh, field_cache(d, amp, seed))
+    rf = fresh.fix(V, 1.7, 1e-8, 3000)
+    assert r["converged"] and r["theta"] < 1e-8
+    assert r["iters"] == rf["iters"] and torch.equal(U, V)
+
+
 def test_fp32_reaches_target_and_tracks_fp64(gf, oracle_lib, field_cache):
     dims = (8, 8, 8, 8)
     U = field_cache(dims, 0.5, 14)
