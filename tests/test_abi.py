@@ -39,6 +39,10 @@ def test_invalid_arguments_fail_before_device_use(gf):
     for dims in [(3, 4, 4, 4), (4, 4, 4, 0), (4, 4, 5, 4), (4, -2, 4, 4)]:
         rc = gf.lib.gf_create(ctypes.byref(h), gf._dims_arr(dims), 3, 0, gf.F32, None, ctypes.byref(p))
         assert rc == gf.EINVAL and not h.value
+    # the largest lattice: 4V link indices must fit 31 bits
+    for dims in [(256, 256, 256, 128), (2, 2, 2, 1 << 28)]:
+        rc = gf.lib.gf_create(ctypes.byref(h), gf._dims_arr(dims), 3, 0, gf.F32, None, ctypes.byref(p))
+        assert rc == gf.EINVAL and not h.value
     for nc in (1, 5, 8):
         assert gf.lib.gf_create(ctypes.byref(h), gf._dims_arr((4, 4, 4, 4)), nc, 0, gf.F32, None,
                                 ctypes.byref(p)) == gf.EUNSUPPORTED

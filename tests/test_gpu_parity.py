@@ -242,6 +242,29 @@ def test_batch_fix_equals_single_fix(gf, field_cache, use_graph):
         assert torch.equal(singles[i], Us[i])
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("diag", [(1, 1, 1), (-1, -1, 1), (1j, 1j, -1)])
+def test_degenerate_constant_fields(gf, oracle_lib, prec, gauge, diag):
+    """Constant diagonal links make every staple block degenerate in some
+    subgroup: the unit field (b = 0 vector part, g = 1), diag(-1, -1, 1)
+    (g = -1, over-rotated about the third axis) and diag(i, i, -1) (a zero
+    SU(2) part, G = 1). One sweep on the GPU equals the oracle's."""
+    dims = (4, 2, 2, 4)
+    U = np.zeros((4, 2, 2, 4, 4, 3, 3), dtype=np.complex128)
+    U[..., range(3), range(3)] = np.array(diag)
+    ctx = make_ctx(gf, dims, gauge, prec)
+    Ug = to_gpu(ctx, U)
+    ctx.sweeps(Ug, 1.7, 1)
+    ref = U.copy()
+    oracle_lib.sweep(ref, dims, 1.7, gauge)
+    got = to_host(ctx, Ug)
+    assert np.abs(got - ref).max() < (1e-14 if prec == 0 else 1e-6)
+    F, th = ctx.quality(Ug)
+    Fo, tho = oracle_lib.quality(got, dims, gauge)  # the GPU's own field, promoted exactly
+    assert abs(F - Fo) < 1e-13 and abs(th - tho) <= 1e-13 * max(tho, 1.0)
+
+
 def test_graph_replay_follows_a_new_eps(gf, field_cache):
     """A context that replayed graphs for one threshold gives, for another
     threshold, exactly what a fresh context gives (the captured check period
