@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["sweep.hip", "su3_device.hpp", "gf_math.hpp", "gf_internal.hpp"]
+KERNEL_SOURCES = ["sweep.hip", "su3_device.hpp", "gf_math.hpp", "gf_internal.hpp", "link8.hpp"]
 
 
 def log(msg):
@@ -201,12 +201,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--omega", type=float, default=1.7)
     ap.add_argument("--sweeps-per-step", type=int, default=10)
-    ap.add_argument("--storage", type=int, choices=[18, 12], default=18)
+    ap.add_argument("--storage", type=int, choices=[18, 12, 8], default=18)
     ap.add_argument("--lps", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--nontemporal", type=int, default=-1)
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-12real", action="store_true", help="skip the 12-real FP32 storage leg")
+    ap.add_argument("--no-8real", action="store_true", help="skip the 8-real FP32 storage leg")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation timing leg")
@@ -239,7 +240,7 @@ def main():
         return
     V = dims[0] * dims[1] * dims[2] * dims[3]
     spp = args.sweeps_per_step
-    storage = gf.STORE_12 if args.storage == 12 else gf.STORE_18
+    storage = {12: gf.STORE_12, 8: gf.STORE_8}.get(args.storage, gf.STORE_18)
     log(f"generating {dims} amp {args.amp} seed {args.seed} (FP64, on the GPU)")
     t = time.perf_counter()
     U64 = synth.random_gauge_field(dims, args.amp, args.seed, device="cuda")
@@ -341,6 +342,23 @@ def main():
             "avg_launch_us": rf12["avg_launch_s"] * 1e6,
             "traffic": measured_traffic(f"halfsweep_{'x'.join(map(str, dims))}_f32_12real_pmc.txt", khash),
             "schedule": r12["schedule"],
+        }
+
+    if args.storage == 18 and not args.no_8real:
+        log("timed FP32 run, 8-real storage (U01, U02, U10 and two phases stored)")
+        r8 = timed_run(gf.F32, gf.STORE_8)
+        rf8 = roofline(r8, gf.F32, 8)
+        out["fp32_8real"] = {
+            "value": V * spp * args.steps / r8["wall"],
+            "unit": "site-sweeps/s",
+            "achieved_gbs": rf8["achieved_gbs"],
+            "frac": rf8["achieved_gbs"] / PEAK_HBM_GBS,
+            "algorithmic_bytes_per_launch": rf8["bytes_per_launch"],
+            "avg_launch_us": rf8["avg_launch_s"] * 1e6,
+            "traffic": measured_traffic(f"halfsweep_{'x'.join(map(str, dims))}_f32_8real_pmc.txt", khash),
+            "schedule": r8["schedule"],
+            "F_after_timed_steps": r8["F"],
+            "F_18real_after_timed_steps": r32["F"],
         }
 
     if not args.no_fp64:

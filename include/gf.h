@@ -39,7 +39,17 @@
  *   (units of one complex: float2 for F32, double2 for F64), with
  *   nb = ceil(V / 128) blocks per parity and ne = 9 (18-real storage) or 6
  *   (12-real storage, gf_params.storage = GF_STORE_12: rows 0 and 1 only, row
- *   2 rebuilt as conj(row0 x row1)). The last block of a parity is padded.
+ *   2 rebuilt as conj(row0 x row1)) or 4 (8-real storage, GF_STORE_8:
+ *   e = 0, 1, 2 hold U01, U02, U10 and e = 3 holds the pair (phase code of
+ *   U00, phase code of U20), where the code of z with w = z/|z| is
+ *   t = Im w / (1 + |Re w|) if Re w >= 0, else 2 - t (t >= 0) or -2 - t
+ *   (t < 0), and 0 for z = 0; the rest follows from unitarity and det U = 1:
+ *   |U00|^2 = 1 - n2, |U20|^2 = n2 - |U10|^2 with n2 = |U01|^2 + |U02|^2,
+ *   U11 = -(conj(U00) U01 U10 + conj(U02) conj(U20)) / n2,
+ *   U12 = (conj(U01) conj(U20) - conj(U00) U02 U10) / n2,
+ *   U21 = -conj(U00 U12 - U02 U10), U22 = conj(U00 U11 - U01 U10); a link
+ *   with U01 = U02 = 0 exactly cannot be held and reads back as
+ *   diag(U00, conj(U00), 1)). The last block of a parity is padded.
  * - SU(N): a single-lattice context may also hold N = 2 or 4 colours (the
  *   paper's method for general N: all N(N-1)/2 SU(2) subgroups (a, b), a < b,
  *   in lexicographic order). Its links are full N x N matrices in the same
@@ -77,7 +87,7 @@ extern "C" {
 
 enum gf_gauge { GF_LANDAU = 0, GF_COULOMB = 1 };
 enum gf_prec { GF_F64 = 0, GF_F32 = 1 };
-enum gf_storage { GF_STORE_18 = 0, GF_STORE_12 = 1 };
+enum gf_storage { GF_STORE_18 = 0, GF_STORE_12 = 1, GF_STORE_8 = 2 };
 
 typedef struct gf_ctx gf_ctx;
 
@@ -91,7 +101,7 @@ typedef struct gf_params {
                                half-sweep, so it costs no extra memory traffic */
     long long start_sweep;  /* global index of the last sweep already done
                                (sets the reunitarisation phase on resume) */
-    int storage;            /* GF_STORE_18 (default) or GF_STORE_12 */
+    int storage;            /* GF_STORE_18 (default), GF_STORE_12 or GF_STORE_8 */
     int lanes_per_site;     /* 0 = default (1; 2 for SU(4) and double SU(2)),
                                else 1, 2, 4 or 8 lanes per site (SU(4): >= 2) */
     int block_threads;      /* 0 = default, else 64, 128, 192 or 256 */
@@ -247,6 +257,13 @@ void gf_host_su2_step(const double b[4], double omega, double r[4]);
 /* The kernels' own double-precision sine/cosine (valid for x in [0, 2 pi])
  * and arctangent: out = {sin x, cos x, atan2(y, x)}. */
 void gf_host_trig(double x, double y, double out[3]);
+
+/* The 8-real storage round trip on the host with the kernels' code: in is a
+ * 3x3 complex matrix as 18 doubles (re, im of element 3 row + col); in
+ * precision prec (GF_F32 first rounds it to float) it is compressed to the
+ * 8 stored reals (written to stored) and reconstructed (written to out).
+ * Returns GF_EINVAL for NULL pointers or a bad precision. */
+int gf_host_link8(int prec, const double in[18], double stored[8], double out[18]);
 
 /* Index check: complex offsets of element 0 of the eight links (18-real
  * storage) that the site (parity, h) of a dims lattice updates in a

@@ -20,6 +20,7 @@
 #include "gf.h"
 #include "gf_internal.hpp"
 #include "gf_math.hpp"
+#include "link8.hpp"
 #include "sun_internal.hpp"
 
 using namespace gf;
@@ -142,7 +143,7 @@ Schedule default_schedule(int prec, int nc, const gf_params &p) {
     Schedule s;
     s.lps = p.lanes_per_site > 0 ? p.lanes_per_site : ((nc == 4 || (nc == 2 && prec == GF_F64)) ? 2 : 1);
     s.block = p.block_threads > 0 ? p.block_threads
-                                   : ((prec == GF_F32 && p.storage == GF_STORE_12) ? 256 : 128);
+                                   : ((prec == GF_F32 && p.storage != GF_STORE_18) ? 256 : 128);
     s.nt = p.nontemporal >= 0 ? p.nontemporal : 1;
     return s;
 }
@@ -297,8 +298,8 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
     if (pp) p = *pp;
     if (p.check_every < 1) p.check_every = 1;
     if (p.reunit_every < 0) return GF_EINVAL;
-    if (p.storage != GF_STORE_18 && p.storage != GF_STORE_12) return GF_EINVAL;
-    if (nc != 3 && p.storage != GF_STORE_18) return GF_EUNSUPPORTED;  // 12-real is SU(3) only
+    if (p.storage != GF_STORE_18 && p.storage != GF_STORE_12 && p.storage != GF_STORE_8) return GF_EINVAL;
+    if (nc != 3 && p.storage != GF_STORE_18) return GF_EUNSUPPORTED;  // 12-/8-real are SU(3) only
     Schedule s = default_schedule(prec, nc, p);
     if (check_schedule(&tmp, s, nc) != GF_OK) return GF_EINVAL;
 
@@ -306,7 +307,7 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
     ctx->n = n;
     ctx->prec = prec;
     ctx->nc = nc;
-    ctx->nelem = nc != 3 ? nc * nc : (p.storage == GF_STORE_12 ? 6 : 9);
+    ctx->nelem = nc != 3 ? nc * nc : (p.storage == GF_STORE_12 ? 6 : p.storage == GF_STORE_8 ? 4 : 9);
     ctx->stream = (hipStream_t)stream;
     ctx->p = p;
     ctx->sched = s;
@@ -996,6 +997,26 @@ void gf_host_trig(double x, double y, double out[3]) {
     if (!out) return;
     gf_sincos(x, &out[0], &out[1]);
     out[2] = gf_atan2(y, x);
+}
+
+int gf_host_link8(int prec, const double in[18], double stored[8], double out[18]) {
+    if (!in || !stored || !out || (prec != GF_F64 && prec != GF_F32)) return GF_EINVAL;
+    if (prec == GF_F64) {
+        double re[9], im[9], sre[4], sim[4];
+        for (int e = 0; e < 9; e++) { re[e] = in[2 * e]; im[e] = in[2 * e + 1]; }
+        link8_compress<double>(re, im, sre, sim);
+        link8_reconstruct<double>(sre, sim, re, im);
+        for (int e = 0; e < 4; e++) { stored[2 * e] = sre[e]; stored[2 * e + 1] = sim[e]; }
+        for (int e = 0; e < 9; e++) { out[2 * e] = re[e]; out[2 * e + 1] = im[e]; }
+    } else {
+        float re[9], im[9], sre[4], sim[4];
+        for (int e = 0; e < 9; e++) { re[e] = (float)in[2 * e]; im[e] = (float)in[2 * e + 1]; }
+        link8_compress<float>(re, im, sre, sim);
+        link8_reconstruct<float>(sre, sim, re, im);
+        for (int e = 0; e < 4; e++) { stored[2 * e] = sre[e]; stored[2 * e + 1] = sim[e]; }
+        for (int e = 0; e < 9; e++) { out[2 * e] = re[e]; out[2 * e + 1] = im[e]; }
+    }
+    return GF_OK;
 }
 
 

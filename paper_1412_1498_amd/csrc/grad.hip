@@ -321,8 +321,8 @@ hipError_t launch_functional(int prec, int nelem, int gauge, const Geom &g, cons
 #define GF_L(R, NE)                                                                               \
     hipLaunchKernelGGL((k_functional<R, NE>), grid, dim3(GB), 0, st, g, nd,                       \
                        (const V2<R>::type *)U, (const V2<R>::type *)gfield, d_partials)
-    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else GF_L(double, 6); }
-    else { if (nelem == 9) GF_L(float, 9); else GF_L(float, 6); }
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
+    else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L
     return hipGetLastError();
 }
@@ -341,8 +341,8 @@ hipError_t launch_functional_grad(int prec, int nelem, int gauge, const Geom &g,
     hipLaunchKernelGGL((k_functional_grad<R, NE>), grid, dim3(GB), 0, st, g, nd,                  \
                        (const V2<R>::type *)U, (const R *)s, (const V2<R>::type *)gfield, scale,   \
                        (R *)grad)
-    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else GF_L(double, 6); }
-    else { if (nelem == 9) GF_L(float, 9); else GF_L(float, 6); }
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
+    else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L
     return hipGetLastError();
 }
@@ -353,8 +353,8 @@ hipError_t launch_gauge_transform(int prec, int nelem, const Geom &g, void *U, c
 #define GF_L(R, NE)                                                                               \
     hipLaunchKernelGGL((k_gauge_transform<R, NE>), grid, dim3(GB), 0, st, g, (V2<R>::type *)U,     \
                        (const V2<R>::type *)gfield)
-    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else GF_L(double, 6); }
-    else { if (nelem == 9) GF_L(float, 9); else GF_L(float, 6); }
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
+    else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L
     return hipGetLastError();
 }

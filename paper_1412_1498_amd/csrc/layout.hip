@@ -23,8 +23,13 @@ __global__ void k_pack(Geom g, const typename V2<R>::type *__restrict__ aos,
     const typename V2<R>::type *src = aos + idx * 9;
     typename V2<R>::type *dst = const_cast<typename V2<R>::type *>(aos) + idx * 9;
     if (!unpack) {
+        Mat<R> m;
 #pragma unroll
-        for (int e = 0; e < NE; e++) U[off + (long long)e * BLK] = src[e];
+        for (int e = 0; e < 9; e++) {
+            m.re[e] = src[e].x;
+            m.im[e] = src[e].y;
+        }
+        store_link<R, NE, false>(m, as_global((void *)U), off);
     } else {
         Mat<R> m;
         load_link<R, NE, false>(m, as_global((const void *)U), off);
@@ -81,8 +86,8 @@ hipError_t launch_pack(int prec, int nelem, const Geom &g, const void *aos, void
 #define GF_L(R, NE)                                                                              \
     hipLaunchKernelGGL((k_pack<R, NE>), grid, dim3(B), 0, st, g,                                 \
                        (const typename V2<R>::type *)aos, (typename V2<R>::type *)U, unpack)
-    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else GF_L(double, 6); }
-    else { if (nelem == 9) GF_L(float, 9); else GF_L(float, 6); }
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
+    else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L
     return hipGetLastError();
 }
@@ -93,8 +98,8 @@ hipError_t launch_reunit(int prec, int nelem, const Geom &g, void *U, hipStream_
     const dim3 grid((unsigned)((n + B - 1) / B));
 #define GF_L(R, NE) \
     hipLaunchKernelGGL((k_reunit<R, NE>), grid, dim3(B), 0, st, g, (typename V2<R>::type *)U)
-    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else GF_L(double, 6); }
-    else { if (nelem == 9) GF_L(float, 9); else GF_L(float, 6); }
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
+    else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L
     return hipGetLastError();
 }

@@ -155,11 +155,13 @@ static hipError_t launch_q(const CfgDesc *d_desc, const int *d_qtile_cfg, const 
 
 hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int *d_qtile_cfg,
                           const int *d_active, int nqtiles, double *d_partials, hipStream_t st) {
-    if (prec == 0)
-        return nelem == 9 ? launch_q<double, 9>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st)
-                          : launch_q<double, 6>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st);
-    return nelem == 9 ? launch_q<float, 9>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st)
-                      : launch_q<float, 6>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st);
+#define GF_Q3(R)                                                                                  \
+    (nelem == 9   ? launch_q<R, 9>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st)           \
+     : nelem == 6 ? launch_q<R, 6>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st)           \
+                  : launch_q<R, 4>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st))
+    const hipError_t e = prec == 0 ? GF_Q3(double) : GF_Q3(float);
+#undef GF_Q3
+    return e;
 }
 
 hipError_t launch_quality_final(const CfgDesc *d_desc, int n, const double *d_partials,

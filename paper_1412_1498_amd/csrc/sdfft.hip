@@ -142,8 +142,8 @@ hipError_t launch_sd_delta(int prec, int nelem, int gauge, const Geom &g, const 
 #define GF_L(R, NE)                                                                              \
     hipLaunchKernelGGL((k_sd_delta<R, NE>), grid, dim3(B), 0, st, g, nd,                         \
                        (const V2<R>::type *)U, (R *)d)
-    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else GF_L(double, 6); }
-    else { if (nelem == 9) GF_L(float, 9); else GF_L(float, 6); }
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
+    else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L
     return hipGetLastError();
 }

@@ -8,6 +8,7 @@
 
 #include "gf_internal.hpp"
 #include "gf_math.hpp"
+#include "link8.hpp"
 
 namespace gf {
 
@@ -63,30 +64,54 @@ __device__ __forceinline__ void rebuild_row2(Mat<R> &m) {
 }
 
 // Link whose element 0 sits at complex offset `off` (see link_off); element
-// e is BLK complex values further. NE = 9: full matrix; NE = 6: rows 0, 1.
+// e is BLK complex values further. NE = 9: full matrix; NE = 6: rows 0, 1;
+// NE = 4: the 8-real form of link8.hpp.
 template <typename R, int NE, bool NT>
 __device__ __forceinline__ void load_link(Mat<R> &m, const gchar *base, long long off) {
     typedef typename V2<R>::type v2;
     const gchar *p = base + off * (long long)sizeof(v2);
+    if constexpr (NE == 4) {
+        R sre[4], sim[4];
 #pragma unroll
-    for (int e = 0; e < NE; e++) {
-        v2 v = ld<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)));
-        m.re[e] = v.x;
-        m.im[e] = v.y;
+        for (int e = 0; e < 4; e++) {
+            v2 v = ld<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)));
+            sre[e] = v.x;
+            sim[e] = v.y;
+        }
+        link8_reconstruct<R>(sre, sim, m.re, m.im);
+    } else {
+#pragma unroll
+        for (int e = 0; e < NE; e++) {
+            v2 v = ld<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)));
+            m.re[e] = v.x;
+            m.im[e] = v.y;
+        }
+        if constexpr (NE == 6) rebuild_row2(m);
     }
-    if constexpr (NE == 6) rebuild_row2(m);
 }
 
 template <typename R, int NE, bool NT>
 __device__ __forceinline__ void store_link(const Mat<R> &m, gchar *base, long long off) {
     typedef typename V2<R>::type v2;
     gchar *p = base + off * (long long)sizeof(v2);
+    if constexpr (NE == 4) {
+        R sre[4], sim[4];
+        link8_compress<R>(m.re, m.im, sre, sim);
 #pragma unroll
-    for (int e = 0; e < NE; e++) {
-        v2 v;
-        v.x = m.re[e];
-        v.y = m.im[e];
-        st<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)), v);
+        for (int e = 0; e < 4; e++) {
+            v2 v;
+            v.x = sre[e];
+            v.y = sim[e];
+            st<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)), v);
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < NE; e++) {
+            v2 v;
+            v.x = m.re[e];
+            v.y = m.im[e];
+            st<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)), v);
+        }
     }
 }
 

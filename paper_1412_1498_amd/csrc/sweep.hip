@@ -219,7 +219,7 @@ __device__ __forceinline__ void or_site(const CfgDesc &d, int p, int h, int sub)
 // loop-invariant state stays live across the tile loop, so every tile gets
 // its own workgroup; the dispatcher balances the tiles over the CUs.)
 template <typename R, int NE, int LPS, bool NT, bool RU>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NE == 4 && sizeof(R) == 4) ? 2 : 1)))
 k_half_sweep(const CfgDesc *__restrict__ desc, const int *__restrict__ tile_cfg,
              const int *__restrict__ active, int parity) {
     const int tile = blockIdx.x;
@@ -266,12 +266,13 @@ static hipError_t launch_lps(const Schedule &s, const CfgDesc *d_desc, const int
 hipError_t launch_half_sweep(int prec, int nelem, const Schedule &s, const CfgDesc *d_desc,
                              const int *d_tile_cfg, const int *d_active, int ntiles, int parity,
                              int reunit, hipStream_t st) {
-    if (prec == 0) {
-        return nelem == 9 ? launch_lps<double, 9>(s, d_desc, d_tile_cfg, d_active, ntiles, parity, reunit, st)
-                          : launch_lps<double, 6>(s, d_desc, d_tile_cfg, d_active, ntiles, parity, reunit, st);
-    }
-    return nelem == 9 ? launch_lps<float, 9>(s, d_desc, d_tile_cfg, d_active, ntiles, parity, reunit, st)
-                      : launch_lps<float, 6>(s, d_desc, d_tile_cfg, d_active, ntiles, parity, reunit, st);
+#define GF_S3(R)                                                                                  \
+    (nelem == 9   ? launch_lps<R, 9>(s, d_desc, d_tile_cfg, d_active, ntiles, parity, reunit, st)     \
+     : nelem == 6 ? launch_lps<R, 6>(s, d_desc, d_tile_cfg, d_active, ntiles, parity, reunit, st)     \
+                  : launch_lps<R, 4>(s, d_desc, d_tile_cfg, d_active, ntiles, parity, reunit, st))
+    const hipError_t e = prec == 0 ? GF_S3(double) : GF_S3(float);
+#undef GF_S3
+    return e;
 }
 
 }  // namespace gf

@@ -24,7 +24,7 @@ OK, NOT_CONVERGED = 0, 1
 EINVAL, ENOMEM, EDEVICE, ENONFINITE, EUNSUPPORTED = -1, -2, -3, -4, -5
 LANDAU, COULOMB = 0, 1
 F64, F32 = 0, 1
-STORE_18, STORE_12 = 0, 1
+STORE_18, STORE_12, STORE_8 = 0, 1, 2
 
 _ERRNAMES = {EINVAL: "GF_EINVAL", ENOMEM: "GF_ENOMEM", EDEVICE: "GF_EDEVICE",
              ENONFINITE: "GF_ENONFINITE", EUNSUPPORTED: "GF_EUNSUPPORTED"}
@@ -87,6 +87,7 @@ def _load():
         "gf_sd_fix": (I, [P, P, D, D, I, P, P, P]),
         "gf_host_su2_step": (None, [P, D, P]),
         "gf_host_trig": (None, [D, D, P]),
+        "gf_host_link8": (I, [I, P, P, P]),
         "gf_site_links": (I, [P, I, LL, P]),
     }
     for name, (res, args) in sig.items():
@@ -145,7 +146,7 @@ class Context:
         self.cdtype = torch.complex128 if prec == F64 else torch.complex64
         p = params if params is not None else default_params(prec)
         self.storage = p.storage
-        self.nelem = (6 if p.storage == STORE_12 else 9) if self.nc == 3 else self.nc * self.nc
+        self.nelem = {STORE_12: 6, STORE_8: 4}.get(p.storage, 9) if self.nc == 3 else self.nc * self.nc
         self._h = ctypes.c_void_p()
         sh = _stream_handle(stream)
         if ensemble is None:
@@ -394,6 +395,21 @@ def host_trig(x, y):
     out = (ctypes.c_double * 3)()
     lib.gf_host_trig(float(x), float(y), out)
     return tuple(out)
+
+
+def host_link8(prec, U):
+    """8-real round trip of one 3x3 complex matrix with the kernels' code:
+    returns (the 8 stored reals, the reconstructed 3x3 complex matrix)."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(U, dtype=np.complex128).reshape(9))
+    inp = (ctypes.c_double * 18)(*[v for z in a for v in (z.real, z.imag)])
+    st = (ctypes.c_double * 8)()
+    out = (ctypes.c_double * 18)()
+    rc = lib.gf_host_link8(int(prec), inp, st, out)
+    if rc != OK:
+        raise GFError(rc, "host_link8")
+    o = np.array(out[:])
+    return np.array(st[:]), (o[0::2] + 1j * o[1::2]).reshape(3, 3)
 
 
 def site_links(dims, parity, h):

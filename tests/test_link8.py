@@ -1,0 +1,120 @@
+"""8-real link storage checked on the host with the kernels' own code (the
+library exports it for this) against numpy: the stored reals are the
+documented ones, and the reconstruction from U01, U02, U10 and the phase
+codes of U00, U20 returns the SU(3) matrix it was given, to the precision the
+format allows. (On the GPU the float path takes the hardware reciprocal and
+square root where the host rounds correctly; tests/test_gpu_link8.py bounds
+the difference.)"""
+import cmath
+
+import numpy as np
+import pytest
+
+U64, U32 = 2.0 ** -53, 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def gf():
+    from paper_1412_1498_amd import gf as mod
+    return mod
+
+
+def haar(rng):
+    z = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    q, r = np.linalg.qr(z)
+    q = q * (np.diag(r) / abs(np.diag(r)))
+    return q / np.linalg.det(q) ** (1 / 3)
+
+
+def decode_phase(p):
+    """The unit complex number of a stored phase code (the format's
+    definition: t = Im w / (1 + |Re w|), shifted by 2 when Re w < 0)."""
+    neg = abs(p) > 1
+    t = np.copysign(2 - abs(p), p) if neg else p
+    c = (1 - t * t) / (1 + t * t)
+    return complex(-c if neg else c, 2 * t / (1 + t * t))
+
+
+def near_one(rng, eps):
+    h = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    h = (h + h.conj().T) / 2
+    h -= np.trace(h) / 3 * np.eye(3)
+    w, v = np.linalg.eigh(h)
+    return (v * np.exp(1j * eps * w)) @ v.conj().T
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_stored_reals_are_the_documented_ones(gf, prec):
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        U = haar(rng)
+        Ui = U.astype(np.complex64).astype(np.complex128) if prec == 1 else U
+        st, _ = gf.host_link8(prec, U)
+        assert st[0] + 1j * st[1] == Ui[0, 1] and st[2] + 1j * st[3] == Ui[0, 2]
+        assert st[4] + 1j * st[5] == Ui[1, 0]
+        u = U32 if prec == 1 else U64
+        for k, (r, c) in ((6, (0, 0)), (7, (2, 0))):
+            assert abs(decode_phase(st[k]) - Ui[r, c] / abs(Ui[r, c])) < 8 * u
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_round_trip_returns_the_link(gf, prec):
+    """Haar-random SU(3): the error is a few units of roundoff, amplified
+    only where the format reads a modulus from 1 - (small): by 1/|U00| and
+    1/|U20| (sqrt of a difference) and by 1/sqrt(n2) (the divisor n2 =
+    |U01|^2 + |U02|^2 meets the input's own roundoff). The result is SU(3)."""
+    rng = np.random.default_rng(2)
+    u = U32 if prec == 1 else U64
+    for _ in range(3000):
+        U = haar(rng)
+        Ui = U.astype(np.complex64).astype(np.complex128) if prec == 1 else U
+        _, out = gf.host_link8(prec, U)
+        n2 = abs(U[0, 1]) ** 2 + abs(U[0, 2]) ** 2
+        kappa = 1 + 1 / abs(U[0, 0]) + 1 / abs(U[2, 0]) + 1 / np.sqrt(n2)
+        assert abs(out - Ui).max() <= 8 * u * kappa
+        assert abs(out @ out.conj().T - np.eye(3)).max() < 64 * u * kappa
+        assert abs(np.linalg.det(out) - 1) < 64 * u * kappa
+
+
+def test_fp32_round_trip_near_the_unit_matrix(gf):
+    """Gauge fixing drives links towards 1: from 1e-1 down to 1e-6 away from
+    it the FP32 format keeps every element within 3e-6 (the input itself is
+    only float-exact)."""
+    rng = np.random.default_rng(3)
+    for eps in (1e-1, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        for _ in range(200):
+            U = near_one(rng, eps)
+            _, out = gf.host_link8(1, U)
+            assert abs(out - U.astype(np.complex64)).max() < 3e-6
+
+
+def test_fp64_round_trip_near_the_unit_matrix(gf):
+    """In FP64 the reconstruction moves a link eps away from 1 by about u/eps:
+    it projects the input's own O(u) departure from SU(3) through the divisor
+    n2 ~ eps^2."""
+    rng = np.random.default_rng(4)
+    for eps in (1e-1, 1e-3, 1e-5):
+        for _ in range(100):
+            U = near_one(rng, eps)
+            _, out = gf.host_link8(0, U)
+            assert abs(out - U).max() < 100 * U64 / eps
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_links_without_off_diagonal_row0(gf, prec):
+    """U01 = U02 = 0 exactly: the lower 2x2 block is not stored and reads back
+    as diag(conj U00, 1), which is right for diag(a, conj a, 1) only."""
+    a = cmath.exp(0.3j)
+    D = np.diag([a, a.conjugate(), 1.0])
+    _, out = gf.host_link8(prec, D)
+    assert abs(out - D).max() < 4 * (U32 if prec == 1 else U64)
+    _, out = gf.host_link8(prec, np.diag([1j, 1j, -1.0]))
+    assert abs(out - np.diag([1j, -1j, 1.0])).max() < 4 * (U32 if prec == 1 else U64)
+    # the phase code on the axes and on both sides of the branch at -1
+    for ang in (0.0, np.pi / 2, -np.pi / 2, np.pi, np.pi - 1e-6, -np.pi + 1e-6, np.pi / 2 + 1e-6,
+                np.pi / 2 - 1e-6):
+        z = cmath.exp(1j * ang)
+        st, out = gf.host_link8(prec, np.diag([z, z.conjugate(), 1.0]))
+        zi = complex(np.complex64(z)) if prec == 1 else z
+        assert abs(decode_phase(st[6]) - zi / abs(zi)) < 8 * (U32 if prec == 1 else U64)
+        assert abs(out[0, 0] - zi) < 8 * (U32 if prec == 1 else U64)
