@@ -374,6 +374,18 @@ def main():
             "schedule": r64["schedule"],
         }
         out["fp32_over_fp64_throughput"] = value / out["fp64"]["value"]
+        if not args.no_8real and args.storage == 18:
+            log("timed FP64 run, 8-real storage")
+            r64_8 = timed_run(gf.F64, gf.STORE_8)
+            rf64_8 = roofline(r64_8, gf.F64, 8)
+            out["fp64_8real"] = {
+                "value": V * spp * args.steps / r64_8["wall"],
+                "unit": "site-sweeps/s",
+                "achieved_gbs": rf64_8["achieved_gbs"],
+                "frac": rf64_8["achieved_gbs"] / PEAK_HBM_GBS,
+                "avg_launch_us": rf64_8["avg_launch_s"] * 1e6,
+                "schedule": r64_8["schedule"],
+            }
 
     if not args.no_convergence:
         conv = {}
