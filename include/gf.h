@@ -25,10 +25,13 @@
  *   are visited in the order (0,1), (0,2), (1,2).
  * - Precision: GF_F64 stores and updates links in double. GF_F32 stores and
  *   updates links in float, while the staple sums, the SU(2) solve with its
- *   power, reunitarisation and the F/theta reductions run in double.
- * - Field pointers (U) are caller-owned DEVICE pointers, at least 256-byte
- *   aligned (a torch tensor's data_ptr()), in the internal layout below. The
- *   library never allocates, frees or keeps them beyond a call.
+ *   power, reunitarisation and the F/theta reductions run in double (the
+ *   8-real float form decodes and encodes links in float, with the hardware
+ *   reciprocal and square root).
+ * - Field pointers (U) are caller-owned DEVICE pointers, at least 16-byte
+ *   aligned (GF_EINVAL otherwise; a torch tensor's data_ptr() is 256-byte
+ *   aligned), in the internal layout below. The library never allocates,
+ *   frees or keeps them beyond a call.
  * - Internal link layout. As in the paper's implementation section, sites
  *   are split by parity p = (x + y + z + t) mod 2 and numbered within a
  *   parity by h = (x + nx(y + ny(z + nz t))) / 2. The sites of one parity are
@@ -120,7 +123,7 @@ void gf_params_default(gf_params *p, int prec);
  * or GF_COULOMB; prec is GF_F64 or GF_F32; stream is a hipStream_t (NULL =
  * default stream); p may be NULL for defaults.
  * Returns GF_EINVAL for odd or non-positive dims, a bad enum or schedule,
- * GF_EUNSUPPORTED for nc not in {2, 3, 4} or 12-real storage with nc != 3,
+ * GF_EUNSUPPORTED for nc not in {2, 3, 4} or 12-/8-real storage with nc != 3,
  * GF_ENOMEM / GF_EDEVICE on allocation failure (then *out is NULL). On
  * success the context owns its reduction scratch. */
 int gf_create(gf_ctx **out, const int dims[4], int nc, int gauge, int prec, void *stream,
