@@ -101,10 +101,11 @@ __device__ void dm_exp(const DMat &S, DMat &E) {
     for (int e = 0; e < 9; e++) { Y.re[e] = S.re[e] * sc; Y.im[e] = S.im[e] * sc; }
 #pragma unroll
     for (int e = 0; e < 9; e++) { E.re[e] = (e % 4 == 0) ? 1.0 : 0.0; E.im[e] = 0.0; }
+#pragma unroll
     for (int j = 16; j >= 1; j--) {
         DMat T;
         dm_mul(Y, E, T);
-        const double inv = 1.0 / j;
+        const double inv = 1.0 / j;  // a constant once unrolled
 #pragma unroll
         for (int e = 0; e < 9; e++) {
             E.re[e] = ((e % 4 == 0) ? 1.0 : 0.0) + T.re[e] * inv;
@@ -144,7 +145,7 @@ __device__ __forceinline__ void load_u(const typename V2<R>::type *__restrict__ 
 
 // g field (9 complex per site, layout [e][p][h]) from s.
 template <typename R>
-__global__ void k_expS(Geom g, const R *__restrict__ s, typename V2<R>::type *__restrict__ gf) {
+__global__ void __launch_bounds__(256) k_expS(Geom g, const R *__restrict__ s, typename V2<R>::type *__restrict__ gf) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.V) return;
     double sv[8];
@@ -175,8 +176,8 @@ __device__ __forceinline__ double block_sum(double v) {
 }
 
 // Per-workgroup partial sums of Re Tr[g(x) U_mu(x) g(x+mu)^dagger].
-template <typename R, int NE>
-__global__ void k_functional(Geom g, int nd, const typename V2<R>::type *__restrict__ U,
+template <typename R, int NE, int ND>
+__global__ void __launch_bounds__(256) k_functional(Geom g, const typename V2<R>::type *__restrict__ U,
                              const typename V2<R>::type *__restrict__ gf, double *__restrict__ part) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     double f = 0.0;
@@ -185,7 +186,8 @@ __global__ void k_functional(Geom g, int nd, const typename V2<R>::type *__restr
         const SiteNbr fw = site_fwd_neighbours(g, p, h);
         DMat gx;
         load_g<R>(gf, g.V, n, gx);
-        for (int mu = 0; mu < nd; mu++) {
+#pragma unroll
+        for (int mu = 0; mu < ND; mu++) {
             DMat u, gu, gy;
             load_u<R, NE>(U, link_off(g, mu, p, h), u);
             load_g<R>(gf, g.V, (1 - p) * g.Vh + pick4(fw.hb, mu), gy);
@@ -198,15 +200,15 @@ __global__ void k_functional(Geom g, int nd, const typename V2<R>::type *__restr
     if (threadIdx.x == 0) part[blockIdx.x] = t;
 }
 
-__global__ void k_sum_partials(const double *__restrict__ part, int n, double *__restrict__ out) {
+__global__ void __launch_bounds__(256) k_sum_partials(const double *__restrict__ part, int n, double *__restrict__ out) {
     double v = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
     const double t = block_sum(v);
     if (threadIdx.x == 0) out[0] = t;
 }
 
-template <typename R, int NE>
-__global__ void k_functional_grad(Geom g, int nd, const typename V2<R>::type *__restrict__ U,
+template <typename R, int NE, int ND>
+__global__ void __launch_bounds__(256) k_functional_grad(Geom g, const typename V2<R>::type *__restrict__ U,
                                   const R *__restrict__ s, const typename V2<R>::type *__restrict__ gf,
                                   double scale, R *__restrict__ grad) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
@@ -217,7 +219,8 @@ __global__ void k_functional_grad(Geom g, int nd, const typename V2<R>::type *__
     DMat K;
 #pragma unroll
     for (int e = 0; e < 9; e++) { K.re[e] = 0.0; K.im[e] = 0.0; }
-    for (int mu = 0; mu < nd; mu++) {
+#pragma unroll
+    for (int mu = 0; mu < ND; mu++) {
         DMat u, gy, t;
         // U_mu(x) g(x+mu)^dagger
         load_u<R, NE>(U, link_off(g, mu, p, h), u);
@@ -273,14 +276,14 @@ __global__ void k_functional_grad(Geom g, int nd, const typename V2<R>::type *__
     tr[5] = Psi.im[7] + Psi.im[5];
     tr[6] = -Psi.re[7] + Psi.re[5];
     tr[7] = r3 * (Psi.im[0] + Psi.im[4] - 2.0 * Psi.im[8]);
-    const double c = scale / (2.0 * nd * 3.0 * (double)g.V);
+    const double c = scale / (2.0 * ND * 3.0 * (double)g.V);
 #pragma unroll
     for (int a = 0; a < 8; a++) grad[(long long)a * g.V + n] = (R)(-tr[a] * c);
 }
 
 // U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger for all four mu.
 template <typename R, int NE>
-__global__ void k_gauge_transform(Geom g, typename V2<R>::type *__restrict__ U,
+__global__ void __launch_bounds__(256) k_gauge_transform(Geom g, typename V2<R>::type *__restrict__ U,
                                   const typename V2<R>::type *__restrict__ gf) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.V) return;
@@ -317,10 +320,15 @@ hipError_t launch_expS(int prec, const Geom &g, const void *s, void *gfield, hip
 hipError_t launch_functional(int prec, int nelem, int gauge, const Geom &g, const void *U,
                              const void *gfield, double *d_partials, hipStream_t st) {
     const dim3 grid((g.V + GB - 1) / GB);
-    const int nd = gauge == 0 ? 4 : 3;
 #define GF_L(R, NE)                                                                               \
-    hipLaunchKernelGGL((k_functional<R, NE>), grid, dim3(GB), 0, st, g, nd,                       \
-                       (const V2<R>::type *)U, (const V2<R>::type *)gfield, d_partials)
+    do {                                                                                          \
+        if (gauge == 0)                                                                           \
+            hipLaunchKernelGGL((k_functional<R, NE, 4>), grid, dim3(GB), 0, st, g,                \
+                               (const V2<R>::type *)U, (const V2<R>::type *)gfield, d_partials);   \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_functional<R, NE, 3>), grid, dim3(GB), 0, st, g,                \
+                               (const V2<R>::type *)U, (const V2<R>::type *)gfield, d_partials);   \
+    } while (0)
     if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
     else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L
@@ -336,11 +344,17 @@ hipError_t launch_functional_grad(int prec, int nelem, int gauge, const Geom &g,
                                   const void *s, const void *gfield, double scale, void *grad,
                                   hipStream_t st) {
     const dim3 grid((g.V + GB - 1) / GB);
-    const int nd = gauge == 0 ? 4 : 3;
 #define GF_L(R, NE)                                                                               \
-    hipLaunchKernelGGL((k_functional_grad<R, NE>), grid, dim3(GB), 0, st, g, nd,                  \
-                       (const V2<R>::type *)U, (const R *)s, (const V2<R>::type *)gfield, scale,   \
-                       (R *)grad)
+    do {                                                                                          \
+        if (gauge == 0)                                                                           \
+            hipLaunchKernelGGL((k_functional_grad<R, NE, 4>), grid, dim3(GB), 0, st, g,           \
+                               (const V2<R>::type *)U, (const R *)s, (const V2<R>::type *)gfield,  \
+                               scale, (R *)grad);                                                 \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_functional_grad<R, NE, 3>), grid, dim3(GB), 0, st, g,           \
+                               (const V2<R>::type *)U, (const R *)s, (const V2<R>::type *)gfield,  \
+                               scale, (R *)grad);                                                 \
+    } while (0)
     if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
     else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L

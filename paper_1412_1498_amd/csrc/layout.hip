@@ -8,7 +8,7 @@ namespace gf {
 
 // One lane per (site, mu) link.
 template <typename R, int NE>
-__global__ void k_pack(Geom g, const typename V2<R>::type *__restrict__ aos,
+__global__ void __launch_bounds__(256) k_pack(Geom g, const typename V2<R>::type *__restrict__ aos,
                        typename V2<R>::type *__restrict__ U, int unpack) {
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= 4LL * g.V) return;
@@ -45,7 +45,7 @@ __global__ void k_pack(Geom g, const typename V2<R>::type *__restrict__ aos,
 
 // One lane per (mu, site) link.
 template <typename R, int NE>
-__global__ void k_reunit(Geom g, typename V2<R>::type *__restrict__ U) {
+__global__ void __launch_bounds__(256) k_reunit(Geom g, typename V2<R>::type *__restrict__ U) {
     const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= 4LL * g.V) return;
     const int mu = (int)(l / g.V);
@@ -60,7 +60,7 @@ __global__ void k_reunit(Geom g, typename V2<R>::type *__restrict__ U) {
 
 // One lane per site: canonical s[site][a] <-> internal s[a][p][h].
 template <typename R>
-__global__ void k_pack_alg(Geom g, const R *__restrict__ aos, R *__restrict__ s, int unpack) {
+__global__ void __launch_bounds__(256) k_pack_alg(Geom g, const R *__restrict__ aos, R *__restrict__ s, int unpack) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.V) return;
     const int x = n % g.nx;

@@ -24,7 +24,7 @@ __device__ __forceinline__ int lex_of(const Geom &g, int p, int h) {
 
 // d[a][lex] = Tr[lambda_a Delta(x)] / (2i) for every site, Delta of eq. (3).
 template <typename R, int NE>
-__global__ void k_sd_delta(Geom g, int nd, const typename V2<R>::type *__restrict__ Uv,
+__global__ void __launch_bounds__(256) k_sd_delta(Geom g, int nd, const typename V2<R>::type *__restrict__ Uv,
                            R *__restrict__ d) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.V) return;
@@ -73,7 +73,7 @@ __global__ void k_sd_delta(Geom g, int nd, const typename V2<R>::type *__restric
 // Spectrum layout [a][t][z][y][kx], kx = 0..nx/2 (half spectrum of the real
 // transform along x). Multiply by scale * p2max / p^2(k), zero mode -> 0.
 template <typename C>
-__global__ void k_sd_filter(Geom g, int with_t, C *__restrict__ spec, double scale, double p2max) {
+__global__ void __launch_bounds__(256) k_sd_filter(Geom g, int with_t, C *__restrict__ spec, double scale, double p2max) {
     const int nkx = g.nx / 2 + 1;
     const long long per = (long long)g.nt * g.nz * g.ny * nkx;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -98,7 +98,7 @@ __global__ void k_sd_filter(Geom g, int with_t, C *__restrict__ spec, double sca
 // g(x) = reunit(1 + i sum_a d_a lambda_a) in double, stored as the g field
 // [e][p][h] (9 complex per site) in the context precision.
 template <typename R>
-__global__ void k_sd_gfield(Geom g, const R *__restrict__ d, typename V2<R>::type *__restrict__ gf) {
+__global__ void __launch_bounds__(256) k_sd_gfield(Geom g, const R *__restrict__ d, typename V2<R>::type *__restrict__ gf) {
     const int n = blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= g.V) return;
     const int p = n >= g.Vh, h = n - p * g.Vh;

@@ -236,7 +236,7 @@ hipError_t launch_sun_lps(const Schedule &s, const CfgDesc *d_desc, const int *d
 
 // Canonical AoS [site][mu][N][N] <-> blocked layout; one thread per link.
 template <typename R, int N>
-__global__ void k_sun_pack(Geom g, const typename V2<R>::type *__restrict__ src,
+__global__ void __launch_bounds__(256) k_sun_pack(Geom g, const typename V2<R>::type *__restrict__ src,
                            typename V2<R>::type *__restrict__ dst, int to_aos) {
     const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= 4LL * g.V) return;
@@ -254,7 +254,7 @@ __global__ void k_sun_pack(Geom g, const typename V2<R>::type *__restrict__ src,
 
 // Standalone reunitarisation of every link; one thread per link.
 template <typename R, int N>
-__global__ void k_sun_reunit(Geom g, void *Uv) {
+__global__ void __launch_bounds__(256) k_sun_reunit(Geom g, void *Uv) {
     const long long l = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= 4LL * g.V) return;
     const int n = (int)(l >> 2), mu = (int)(l & 3);
