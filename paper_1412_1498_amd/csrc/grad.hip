@@ -10,6 +10,7 @@
 // one series on a 3x3 matrix per site followed by eight traces. At s = 0 it
 // reduces to Re Tr[X_a K(x)] / (d N_c V).
 #include "su3_device.hpp"
+#include "tile_order.hpp"
 
 namespace gf {
 
@@ -281,13 +282,21 @@ __global__ void __launch_bounds__(256) k_functional_grad(Geom g, const typename 
     for (int a = 0; a < 8; a++) grad[(long long)a * g.V + n] = (R)(-tr[a] * c);
 }
 
-// U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger for all four mu.
+// U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger for all four mu. A workgroup takes
+// GT_TILE/2 half-indices in both parities, so the g(x+mu) it reads (the other
+// parity, nearby h) were mostly brought into cache by its own g(x) reads;
+// tiles are dealt XCD-contiguously.
+constexpr int GT_TILE = 256;
+
 template <typename R, int NE>
-__global__ void __launch_bounds__(256) k_gauge_transform(Geom g, typename V2<R>::type *__restrict__ U,
+__global__ void __launch_bounds__(GT_TILE) k_gauge_transform(Geom g, typename V2<R>::type *__restrict__ U,
                                   const typename V2<R>::type *__restrict__ gf) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.V) return;
-    const int p = n >= g.Vh, h = n - p * g.Vh;
+    constexpr int QH = GT_TILE / 2;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int p = threadIdx.x >= QH;
+    const int h = tile * QH + (int)threadIdx.x - p * QH;
+    if (h >= g.Vh) return;
+    const int n = p * g.Vh + h;
     const SiteNbr fw = site_fwd_neighbours(g, p, h);
     DMat gx;
     load_g<R>(gf, g.V, n, gx);
@@ -363,9 +372,9 @@ hipError_t launch_functional_grad(int prec, int nelem, int gauge, const Geom &g,
 
 hipError_t launch_gauge_transform(int prec, int nelem, const Geom &g, void *U, const void *gfield,
                                   hipStream_t st) {
-    const dim3 grid((g.V + GB - 1) / GB);
+    const dim3 grid((g.Vh + GT_TILE / 2 - 1) / (GT_TILE / 2));
 #define GF_L(R, NE)                                                                               \
-    hipLaunchKernelGGL((k_gauge_transform<R, NE>), grid, dim3(GB), 0, st, g, (V2<R>::type *)U,     \
+    hipLaunchKernelGGL((k_gauge_transform<R, NE>), grid, dim3(GT_TILE), 0, st, g, (V2<R>::type *)U, \
                        (const V2<R>::type *)gfield)
     if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
     else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }

@@ -19,6 +19,7 @@
 #include "su3_device.hpp"
 #include "sun_device.hpp"
 #include "sun_internal.hpp"
+#include "tile_order.hpp"
 
 namespace gf {
 
@@ -44,16 +45,6 @@ __device__ __forceinline__ void block_sum2(double &a, double &b) {
         a = ta;
         b = tb;
     }
-}
-
-// Workgroups are dispatched to the 8 XCDs round-robin by id. Map id b of n
-// to a tile so that XCD k gets the k-th contiguous share of the tiles, in
-// order (a bijection of [0, n) for any n).
-__device__ __forceinline__ int xcd_tile(int b, int n) {
-    constexpr int NX = 8;
-    const int x = b % NX, i = b / NX;
-    const int q = n / NX, r = n % NX;
-    return x * q + min(x, r) + i;
 }
 
 template <typename R, int NE>

@@ -9,6 +9,7 @@
 // d_a = Tr[lambda_a Delta] / (2i) real, so filtering the eight real d_a is
 // the same linear map as filtering every matrix element.
 #include "su3_device.hpp"
+#include "tile_order.hpp"
 
 namespace gf {
 
@@ -23,12 +24,22 @@ __device__ __forceinline__ int lex_of(const Geom &g, int p, int h) {
 }
 
 // d[a][lex] = Tr[lambda_a Delta(x)] / (2i) for every site, Delta of eq. (3).
+// A workgroup takes SD_TILE/2 half-indices h in both parities (lanes below
+// SD_TILE/2 even): a site's backward links are the other parity's links at
+// nearby h, which the workgroup's own forward reads bring into cache, and
+// the tile's lexicographic outputs 2h + (x mod 2) fill one contiguous range.
+// Tiles are dealt XCD-contiguously (each XCD's L2 then holds the z
+// neighbours).
+constexpr int SD_TILE = 256;
+
 template <typename R, int NE>
-__global__ void __launch_bounds__(256) k_sd_delta(Geom g, int nd, const typename V2<R>::type *__restrict__ Uv,
+__global__ void __launch_bounds__(SD_TILE) k_sd_delta(Geom g, int nd, const typename V2<R>::type *__restrict__ Uv,
                            R *__restrict__ d) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.V) return;
-    const int p = n >= g.Vh, h = n - p * g.Vh;
+    constexpr int QH = SD_TILE / 2;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int p = threadIdx.x >= QH;
+    const int h = tile * QH + (int)threadIdx.x - p * QH;
+    if (h >= g.Vh) return;
     const SiteNbr nb = site_neighbours(g, p, h);
     const gchar *U = as_global((const void *)Uv);
     double mr[9], mi[9];
@@ -72,13 +83,15 @@ __global__ void __launch_bounds__(256) k_sd_delta(Geom g, int nd, const typename
 
 // Spectrum layout [a][t][z][y][kx], kx = 0..nx/2 (half spectrum of the real
 // transform along x). Multiply by scale * p2max / p^2(k), zero mode -> 0.
+// One thread per mode: the factor is computed once and applied to the eight
+// components.
 template <typename C>
 __global__ void __launch_bounds__(256) k_sd_filter(Geom g, int with_t, C *__restrict__ spec, double scale, double p2max) {
     const int nkx = g.nx / 2 + 1;
     const long long per = (long long)g.nt * g.nz * g.ny * nkx;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= 8 * per) return;
-    long long r = i % per;
+    if (i >= per) return;
+    long long r = i;
     const int kx = (int)(r % nkx); r /= nkx;
     const int ky = (int)(r % g.ny); r /= g.ny;
     const int kz = (int)(r % g.nz); r /= g.nz;
@@ -89,19 +102,26 @@ __global__ void __launch_bounds__(256) k_sd_filter(Geom g, int with_t, C *__rest
     s = sinpi((double)kz / g.nz); p2 += 4.0 * s * s;
     if (with_t) { s = sinpi((double)kt / g.nt); p2 += 4.0 * s * s; }
     const double f = p2 > 0.0 ? scale * p2max / p2 : 0.0;
-    C v = spec[i];
-    v.x = (decltype(v.x))(v.x * f);
-    v.y = (decltype(v.y))(v.y * f);
-    spec[i] = v;
+#pragma unroll
+    for (int a = 0; a < 8; a++) {
+        C v = spec[a * per + i];
+        v.x = (decltype(v.x))(v.x * f);
+        v.y = (decltype(v.y))(v.y * f);
+        spec[a * per + i] = v;
+    }
 }
 
 // g(x) = reunit(1 + i sum_a d_a lambda_a) in double, stored as the g field
 // [e][p][h] (9 complex per site) in the context precision.
+// Tiled like k_sd_delta: the tile's lexicographic reads fill one range.
 template <typename R>
-__global__ void __launch_bounds__(256) k_sd_gfield(Geom g, const R *__restrict__ d, typename V2<R>::type *__restrict__ gf) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= g.V) return;
-    const int p = n >= g.Vh, h = n - p * g.Vh;
+__global__ void __launch_bounds__(SD_TILE) k_sd_gfield(Geom g, const R *__restrict__ d, typename V2<R>::type *__restrict__ gf) {
+    constexpr int QH = SD_TILE / 2;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int p = threadIdx.x >= QH;
+    const int h = tile * QH + (int)threadIdx.x - p * QH;
+    if (h >= g.Vh) return;
+    const int n = p * g.Vh + h;
     const int lx = lex_of(g, p, h);
     double s[8];
 #pragma unroll
@@ -136,8 +156,8 @@ __global__ void __launch_bounds__(256) k_sd_gfield(Geom g, const R *__restrict__
 
 hipError_t launch_sd_delta(int prec, int nelem, int gauge, const Geom &g, const void *U, void *d,
                            hipStream_t st) {
-    const int B = 256;
-    const dim3 grid((g.V + B - 1) / B);
+    const int B = SD_TILE;
+    const dim3 grid((g.Vh + B / 2 - 1) / (B / 2));
     const int nd = gauge == 0 ? 4 : 3;
 #define GF_L(R, NE)                                                                              \
     hipLaunchKernelGGL((k_sd_delta<R, NE>), grid, dim3(B), 0, st, g, nd,                         \
@@ -150,7 +170,7 @@ hipError_t launch_sd_delta(int prec, int nelem, int gauge, const Geom &g, const 
 
 hipError_t launch_sd_filter(int prec, const Geom &g, int with_t, void *spec, double scale,
                             double p2max, hipStream_t st) {
-    const long long n = 8LL * g.nt * g.nz * g.ny * (g.nx / 2 + 1);
+    const long long n = (long long)g.nt * g.nz * g.ny * (g.nx / 2 + 1);
     const int B = 256;
     const dim3 grid((unsigned)((n + B - 1) / B));
     if (prec == 0)
@@ -163,8 +183,8 @@ hipError_t launch_sd_filter(int prec, const Geom &g, int with_t, void *spec, dou
 }
 
 hipError_t launch_sd_gfield(int prec, const Geom &g, const void *d, void *gfield, hipStream_t st) {
-    const int B = 256;
-    const dim3 grid((g.V + B - 1) / B);
+    const int B = SD_TILE;
+    const dim3 grid((g.Vh + B / 2 - 1) / (B / 2));
     if (prec == 0)
         hipLaunchKernelGGL(k_sd_gfield<double>, grid, dim3(B), 0, st, g, (const double *)d,
                            (V2<double>::type *)gfield);
