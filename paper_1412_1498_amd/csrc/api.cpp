@@ -852,8 +852,8 @@ namespace {
     } while (0)
 
 // Buffers and plans: 3D real-to-complex transforms over (z, y, x) batched
-// over the 8 components and the time slices, and (Landau) a strided complex
-// 1D transform along t, applied per component.
+// over the time slices and the 8 components (layout [t][a][z][y][x]), and
+// (Landau) one strided complex 1D transform along t over all of them.
 int sd_prepare(gf_ctx *ctx) {
     if (ctx->sd_ready) return GF_OK;
     int rc;
@@ -894,9 +894,10 @@ int sd_prepare(gf_ctx *ctx) {
                         dp ? HIPFFT_Z2D : HIPFFT_C2R, 8 * g.nt)))
         return rc;
     if (ctx->desc[0].gauge == GF_LANDAU) {
+        // spectrum [t][a][z][y][kx]: the t axis of all 8 components in one call
         int nt1[1] = {g.nt};
-        if ((rc = make_plan(ctx->fft_t, 1, nt1, nt1, (int)S, 1, nt1, (int)S, 1, dp ? HIPFFT_Z2Z : HIPFFT_C2C,
-                            (int)S)))
+        const int cols = (int)(8 * S);
+        if ((rc = make_plan(ctx->fft_t, 1, nt1, nt1, cols, 1, nt1, cols, 1, dp ? HIPFFT_Z2Z : HIPFFT_C2C, cols)))
             return rc;
     }
     ctx->sd_ready = true;
@@ -904,17 +905,12 @@ int sd_prepare(gf_ctx *ctx) {
 }
 
 int sd_t_transform(gf_ctx *ctx, int dir) {
-    const Geom &g = ctx->desc[0].g;
-    const long long S = (long long)g.nz * g.ny * (g.nx / 2 + 1);
-    for (int a = 0; a < 8; a++) {
-        const long long off = (long long)a * g.nt * S;
-        if (ctx->prec == GF_F64) {
-            hipfftDoubleComplex *p = (hipfftDoubleComplex *)ctx->d_spec + off;
-            FFTTRY(ctx, hipfftExecZ2Z(ctx->fft_t, p, p, dir));
-        } else {
-            hipfftComplex *p = (hipfftComplex *)ctx->d_spec + off;
-            FFTTRY(ctx, hipfftExecC2C(ctx->fft_t, p, p, dir));
-        }
+    if (ctx->prec == GF_F64) {
+        hipfftDoubleComplex *p = (hipfftDoubleComplex *)ctx->d_spec;
+        FFTTRY(ctx, hipfftExecZ2Z(ctx->fft_t, p, p, dir));
+    } else {
+        hipfftComplex *p = (hipfftComplex *)ctx->d_spec;
+        FFTTRY(ctx, hipfftExecC2C(ctx->fft_t, p, p, dir));
     }
     return GF_OK;
 }

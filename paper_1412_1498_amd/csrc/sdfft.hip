@@ -23,7 +23,8 @@ __device__ __forceinline__ int lex_of(const Geom &g, int p, int h) {
     return 2 * h + ((p + j + k + t) & 1);
 }
 
-// d[a][lex] = Tr[lambda_a Delta(x)] / (2i) for every site, Delta of eq. (3).
+// d_a(x) = Tr[lambda_a Delta(x)] / (2i) for every site, Delta of eq. (3),
+// stored [t][a][z][y][x].
 // A workgroup takes SD_TILE/2 half-indices h in both parities (lanes below
 // SD_TILE/2 even): a site's backward links are the other parity's links at
 // nearby h, which the workgroup's own forward reads bring into cache, and
@@ -77,18 +78,22 @@ __global__ void __launch_bounds__(SD_TILE) k_sd_delta(Geom g, int nd, const type
     o[6] = 0.5 * (ar[5] - ar[7]);
     o[7] = 0.5 * r3 * (ai[0] + ai[4] - 2.0 * ai[8]);
     const int lx = lex_of(g, p, h);
+    // layout [t][a][z][y][x]: one hipFFT call then covers the t axis of all components
+    const int V3 = g.V / g.nt;
+    const int t = lx / V3, x3 = lx - t * V3;
 #pragma unroll
-    for (int a = 0; a < 8; a++) d[(long long)a * g.V + lx] = (R)o[a];
+    for (int a = 0; a < 8; a++) d[((long long)t * 8 + a) * V3 + x3] = (R)o[a];
 }
 
-// Spectrum layout [a][t][z][y][kx], kx = 0..nx/2 (half spectrum of the real
+// Spectrum layout [t][a][z][y][kx], kx = 0..nx/2 (half spectrum of the real
 // transform along x). Multiply by scale * p2max / p^2(k), zero mode -> 0.
 // One thread per mode: the factor is computed once and applied to the eight
 // components.
 template <typename C>
 __global__ void __launch_bounds__(256) k_sd_filter(Geom g, int with_t, C *__restrict__ spec, double scale, double p2max) {
     const int nkx = g.nx / 2 + 1;
-    const long long per = (long long)g.nt * g.nz * g.ny * nkx;
+    const long long S = (long long)g.nz * g.ny * nkx;
+    const long long per = (long long)g.nt * S;
     const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= per) return;
     long long r = i;
@@ -102,12 +107,13 @@ __global__ void __launch_bounds__(256) k_sd_filter(Geom g, int with_t, C *__rest
     s = sinpi((double)kz / g.nz); p2 += 4.0 * s * s;
     if (with_t) { s = sinpi((double)kt / g.nt); p2 += 4.0 * s * s; }
     const double f = p2 > 0.0 ? scale * p2max / p2 : 0.0;
+    const long long base = (long long)kt * 8 * S + (i - (long long)kt * S);
 #pragma unroll
     for (int a = 0; a < 8; a++) {
-        C v = spec[a * per + i];
+        C v = spec[base + a * S];
         v.x = (decltype(v.x))(v.x * f);
         v.y = (decltype(v.y))(v.y * f);
-        spec[a * per + i] = v;
+        spec[base + a * S] = v;
     }
 }
 
@@ -124,8 +130,10 @@ __global__ void __launch_bounds__(SD_TILE) k_sd_gfield(Geom g, const R *__restri
     const int n = p * g.Vh + h;
     const int lx = lex_of(g, p, h);
     double s[8];
+    const int V3 = g.V / g.nt;
+    const int t = lx / V3, x3 = lx - t * V3;
 #pragma unroll
-    for (int a = 0; a < 8; a++) s[a] = (double)d[(long long)a * g.V + lx];
+    for (int a = 0; a < 8; a++) s[a] = (double)d[((long long)t * 8 + a) * V3 + x3];
     const double r3 = 0.57735026918962576451;
     // H = sum_a s_a lambda_a; 1 + i H
     double hr[9], hi[9];
