@@ -136,10 +136,10 @@ __device__ __forceinline__ void load_g(const typename V2<R>::type *__restrict__ 
     }
 }
 
-template <typename R, int NE>
+template <typename R, int NE, bool NT = false>
 __device__ __forceinline__ void load_u(const typename V2<R>::type *__restrict__ U, long long off, DMat &m) {
     Mat<R> t;
-    load_link<R, NE, false>(t, as_global((const void *)U), off);
+    load_link<R, NE, NT>(t, as_global((const void *)U), off);
 #pragma unroll
     for (int e = 0; e < 9; e++) { m.re[e] = t.re[e]; m.im[e] = t.im[e]; }
 }
@@ -302,14 +302,14 @@ __global__ void __launch_bounds__(GT_TILE) k_gauge_transform(Geom g, typename V2
     load_g<R>(gf, g.V, n, gx);
     for (int mu = 0; mu < 4; mu++) {
         DMat u, gy, t, r;
-        load_u<R, NE>(U, link_off(g, mu, p, h), u);
+        load_u<R, NE, true>(U, link_off(g, mu, p, h), u);  // each link is read and written once: stream
         load_g<R>(gf, g.V, (1 - p) * g.Vh + pick4(fw.hb, mu), gy);
         dm_mul(gx, u, t);
         dm_mul_nd(t, gy, r);
         Mat<R> m;
 #pragma unroll
         for (int e = 0; e < 9; e++) { m.re[e] = (R)r.re[e]; m.im[e] = (R)r.im[e]; }
-        store_link<R, NE, false>(m, as_global((void *)U), link_off(g, mu, p, h));
+        store_link<R, NE, true>(m, as_global((void *)U), link_off(g, mu, p, h));
     }
 }
 
