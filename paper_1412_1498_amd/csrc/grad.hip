@@ -18,16 +18,22 @@ struct DMat {
     double re[9], im[9];
 };
 
+// 3x3 complex products in double, each element an FMA chain (4 per complex
+// multiply-add).
 __device__ __forceinline__ void dm_mul(const DMat &a, const DMat &b, DMat &c) {
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            double r = 0.0, m = 0.0;
+            double r = a.re[3 * i] * b.re[j], m = a.re[3 * i] * b.im[j];
+            r = fma(-a.im[3 * i], b.im[j], r);
+            m = fma(a.im[3 * i], b.re[j], m);
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-                r += a.re[3 * i + k] * b.re[3 * k + j] - a.im[3 * i + k] * b.im[3 * k + j];
-                m += a.re[3 * i + k] * b.im[3 * k + j] + a.im[3 * i + k] * b.re[3 * k + j];
+            for (int k = 1; k < 3; k++) {
+                r = fma(a.re[3 * i + k], b.re[3 * k + j], r);
+                r = fma(-a.im[3 * i + k], b.im[3 * k + j], r);
+                m = fma(a.re[3 * i + k], b.im[3 * k + j], m);
+                m = fma(a.im[3 * i + k], b.re[3 * k + j], m);
             }
             c.re[3 * i + j] = r;
             c.im[3 * i + j] = m;
@@ -40,29 +46,36 @@ __device__ __forceinline__ void dm_mul_nd(const DMat &a, const DMat &b, DMat &c)
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            double r = 0.0, m = 0.0;
+            double r = a.re[3 * i] * b.re[3 * j], m = a.im[3 * i] * b.re[3 * j];
+            r = fma(a.im[3 * i], b.im[3 * j], r);
+            m = fma(-a.re[3 * i], b.im[3 * j], m);
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-                r += a.re[3 * i + k] * b.re[3 * j + k] + a.im[3 * i + k] * b.im[3 * j + k];
-                m += a.im[3 * i + k] * b.re[3 * j + k] - a.re[3 * i + k] * b.im[3 * j + k];
+            for (int k = 1; k < 3; k++) {
+                r = fma(a.re[3 * i + k], b.re[3 * j + k], r);
+                r = fma(a.im[3 * i + k], b.im[3 * j + k], r);
+                m = fma(a.im[3 * i + k], b.re[3 * j + k], m);
+                m = fma(-a.re[3 * i + k], b.im[3 * j + k], m);
             }
             c.re[3 * i + j] = r;
             c.im[3 * i + j] = m;
         }
 }
 
-// a^dagger * b^dagger
+// a^dagger * b^dagger: element (i, j) = sum_k conj(a_ki) conj(b_jk)
 __device__ __forceinline__ void dm_mul_dd(const DMat &a, const DMat &b, DMat &c) {
 #pragma unroll
     for (int i = 0; i < 3; i++)
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-            double r = 0.0, m = 0.0;
+            double r = a.re[i] * b.re[3 * j], m = -a.re[i] * b.im[3 * j];
+            r = fma(-a.im[i], b.im[3 * j], r);
+            m = fma(-a.im[i], b.re[3 * j], m);
 #pragma unroll
-            for (int k = 0; k < 3; k++) {
-                // conj(a_ki) conj(b_jk)
-                r += a.re[3 * k + i] * b.re[3 * j + k] - a.im[3 * k + i] * b.im[3 * j + k];
-                m -= a.re[3 * k + i] * b.im[3 * j + k] + a.im[3 * k + i] * b.re[3 * j + k];
+            for (int k = 1; k < 3; k++) {
+                r = fma(a.re[3 * k + i], b.re[3 * j + k], r);
+                r = fma(-a.im[3 * k + i], b.im[3 * j + k], r);
+                m = fma(-a.re[3 * k + i], b.im[3 * j + k], m);
+                m = fma(-a.im[3 * k + i], b.re[3 * j + k], m);
             }
             c.re[3 * i + j] = r;
             c.im[3 * i + j] = m;
@@ -87,8 +100,10 @@ __device__ __forceinline__ void algebra_matrix(const double s[8], DMat &S) {
     for (int e = 0; e < 9; e++) { S.re[e] = -hi[e]; S.im[e] = hr[e]; }
 }
 
-// exp(S) by scaling and squaring of a degree-16 Taylor polynomial (scaled
-// argument of Frobenius norm <= 1/2).
+// exp(S) by scaling and squaring of a degree-DEG Taylor polynomial (scaled
+// argument of Frobenius norm <= 1/2, so the truncation is below
+// 2^-(DEG+1) / (DEG+1)!: ~1e-20 for DEG = 16, ~1e-11 for DEG = 10).
+template <int DEG>
 __device__ void dm_exp(const DMat &S, DMat &E) {
     double nrm2 = 0.0;
 #pragma unroll
@@ -103,7 +118,7 @@ __device__ void dm_exp(const DMat &S, DMat &E) {
 #pragma unroll
     for (int e = 0; e < 9; e++) { E.re[e] = (e % 4 == 0) ? 1.0 : 0.0; E.im[e] = 0.0; }
 #pragma unroll
-    for (int j = 16; j >= 1; j--) {
+    for (int j = DEG; j >= 1; j--) {
         DMat T;
         dm_mul(Y, E, T);
         const double inv = 1.0 / j;  // a constant once unrolled
@@ -153,7 +168,8 @@ __global__ void __launch_bounds__(256) k_expS(Geom g, const R *__restrict__ s, t
     load_s(s, g.V, n, sv);
     DMat S, E;
     algebra_matrix(sv, S);
-    dm_exp(S, E);
+    // the g field is stored in R: degree 10 is exact to float rounding, 16 to double
+    dm_exp<sizeof(R) == 4 ? 10 : 16>(S, E);
 #pragma unroll
     for (int e = 0; e < 9; e++) {
         typename V2<R>::type v;
@@ -249,6 +265,8 @@ __global__ void __launch_bounds__(256) k_functional_grad(Geom g, const typename 
 #pragma unroll
     for (int e = 0; e < 9; e++) ymax = fmax(ymax, fabs(Y.re[e]) + fabs(Y.im[e]));
     double fact = 1.0;
+    // the series stops once a term is below the output's rounding (float or double)
+    const double tol = sizeof(R) == 4 ? 1e-10 : 1e-18;
     for (int k = 1; k <= 60; k++) {
         DMat A, B;
         dm_mul(S, T, A);
@@ -264,7 +282,7 @@ __global__ void __launch_bounds__(256) k_functional_grad(Geom g, const typename 
         const double inv = 1.0 / fact;
 #pragma unroll
         for (int e = 0; e < 9; e++) { Psi.re[e] += T.re[e] * inv; Psi.im[e] += T.im[e] * inv; }
-        if (tmax * inv <= 1e-18 * ymax) break;
+        if (tmax * inv <= tol * ymax) break;
     }
     // Re Tr[(i lambda_a / 2) Psi] = -Im Tr[lambda_a Psi] / 2
     const double r3 = 0.57735026918962576451;
