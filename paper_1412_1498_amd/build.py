@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libgf.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("GF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "sweep.hip", "quality.hip", "layout.hip", "grad.hip", "sdfft.hip", "sun.hip"]
+SOURCES = ["api.cpp", "sweep.hip", "quality.hip", "layout.hip", "grad.hip", "sdfft.hip", "fft.hip", "sun.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -49,7 +49,7 @@ def build(verbose: bool = False, extra=()) -> str:
         objs = list(ex.map(lambda s: _compile(s, extra), SOURCES))
     tmp = OUT + f".tmp{os.getpid()}"
     cmd = ["hipcc", "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp, *objs,
-           "-L/opt/rocm/lib", "-lhipfft", "-Wl,-rpath,/opt/rocm/lib"]
+           "-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")

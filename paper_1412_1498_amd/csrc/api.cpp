@@ -3,7 +3,6 @@
 // (with hipGraph replay of a check period), the schedule autotuner and
 // kernel timing. All device work goes to the context's stream.
 #include <hip/hip_runtime.h>
-#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -63,11 +62,11 @@ struct gf_ctx {
     double *d_fpart = nullptr;
     double *d_fout = nullptr;
     // Fourier-accelerated steepest descent: su(3) components of Delta in
-    // lexicographic order, their spectrum, and the hipFFT plans
+    // lexicographic order, their half spectrum, and the tables of roots of
+    // unity for the x, y, z and t lengths (FFT_MAX_N complex doubles each)
     void *d_sd = nullptr;
     void *d_spec = nullptr;
-    hipfftHandle fft_fwd = 0, fft_inv = 0, fft_t = 0;
-    bool sd_ready = false;
+    void *d_roots = nullptr;
 };
 
 namespace {
@@ -415,11 +414,9 @@ int gf_destroy(gf_ctx *ctx) {
     (void)hipFree(ctx->d_active);
     (void)hipFree(ctx->d_ones);
     (void)hipFree(ctx->d_iters);
-    if (ctx->fft_fwd) (void)hipfftDestroy(ctx->fft_fwd);
-    if (ctx->fft_inv) (void)hipfftDestroy(ctx->fft_inv);
-    if (ctx->fft_t) (void)hipfftDestroy(ctx->fft_t);
     (void)hipFree(ctx->d_sd);
     (void)hipFree(ctx->d_spec);
+    (void)hipFree(ctx->d_roots);
     (void)hipFree(ctx->d_gfield);
     (void)hipFree(ctx->d_fpart);
     (void)hipFree(ctx->d_fout);
@@ -845,24 +842,17 @@ int gf_gauge_transform(gf_ctx *ctx, void *U, const void *s) {
 
 namespace {
 
-#define FFTTRY(ctx, call)                                                                        \
-    do {                                                                                         \
-        hipfftResult r_ = (call);                                                                \
-        if (r_ != HIPFFT_SUCCESS) return fail(ctx, GF_EDEVICE, "%s failed: hipfft status %d", #call, (int)r_); \
-    } while (0)
-
-// Buffers and plans: 3D real-to-complex transforms over (z, y, x) batched
-// over the time slices and the 8 components (layout [t][a][z][y][x]), and
-// (Landau) one strided complex 1D transform along t over all of them.
+// Buffers of one step: the eight real components d[t][a][z][y][x] and their
+// half spectrum spec[t][a][z][y][kx] (kx = 0..nx/2). Made once per context;
+// a call after a failed allocation retries what is missing.
 int sd_prepare(gf_ctx *ctx) {
-    if (ctx->sd_ready) return GF_OK;
+    const Geom &g = ctx->desc[0].g;
+    CHECK(ctx, g.nx <= FFT_MAX_N && g.ny <= FFT_MAX_N && g.nz <= FFT_MAX_N && g.nt <= FFT_MAX_N,
+          GF_EUNSUPPORTED, "Fourier acceleration supports lattice extents up to %d", FFT_MAX_N);
     int rc;
     if ((rc = ensure_diff_scratch(ctx))) return rc;
-    const Geom &g = ctx->desc[0].g;
     const size_t rs = ctx->prec == GF_F64 ? 8 : 4;
     const long long S = (long long)g.nz * g.ny * (g.nx / 2 + 1);
-    // every resource is made only if missing, so a call after a failure
-    // resumes where it stopped instead of leaking what was already made
     if (!ctx->d_sd && hipMalloc(&ctx->d_sd, 8 * (size_t)g.V * rs) != hipSuccess) {
         ctx->d_sd = nullptr;
         return fail(ctx, GF_ENOMEM, "cannot allocate the Fourier acceleration buffers");
@@ -871,71 +861,54 @@ int sd_prepare(gf_ctx *ctx) {
         ctx->d_spec = nullptr;
         return fail(ctx, GF_ENOMEM, "cannot allocate the Fourier acceleration buffers");
     }
-    int n3[3] = {g.nz, g.ny, g.nx};
-    const bool dp = ctx->prec == GF_F64;
-    // a plan is kept only once it was made and bound to the stream
-    auto make_plan = [&](hipfftHandle &out, int rank, int *n, int *inembed, int istride, int idist,
-                         int *onembed, int ostride, int odist, hipfftType type, int batch) -> int {
-        if (out) return GF_OK;
-        hipfftHandle h = 0;
-        hipfftResult r = hipfftPlanMany(&h, rank, n, inembed, istride, idist, onembed, ostride, odist, type, batch);
-        if (r == HIPFFT_SUCCESS) r = hipfftSetStream(h, ctx->stream);
-        if (r != HIPFFT_SUCCESS) {
-            if (h) (void)hipfftDestroy(h);
-            return fail(ctx, GF_EDEVICE, "hipfft plan creation failed: hipfft status %d", (int)r);
+    if (!ctx->d_roots) {
+        void *w = nullptr;
+        if (hipMalloc(&w, 4 * (size_t)FFT_MAX_N * 16) != hipSuccess)
+            return fail(ctx, GF_ENOMEM, "cannot allocate the Fourier acceleration buffers");
+        const int len[4] = {g.nx, g.ny, g.nz, g.nt};
+        for (int a = 0; a < 4; a++) {
+            const hipError_t e = launch_fft_roots((char *)w + (size_t)a * FFT_MAX_N * 16, len[a], ctx->stream);
+            if (e != hipSuccess) {
+                (void)hipFree(w);
+                return fail(ctx, GF_EDEVICE, "root tables: %s", hipGetErrorString(e));
+            }
         }
-        out = h;
-        return GF_OK;
-    };
-    if ((rc = make_plan(ctx->fft_fwd, 3, n3, nullptr, 1, g.nz * g.ny * g.nx, nullptr, 1, (int)S,
-                        dp ? HIPFFT_D2Z : HIPFFT_R2C, 8 * g.nt)))
-        return rc;
-    if ((rc = make_plan(ctx->fft_inv, 3, n3, nullptr, 1, (int)S, nullptr, 1, g.nz * g.ny * g.nx,
-                        dp ? HIPFFT_Z2D : HIPFFT_C2R, 8 * g.nt)))
-        return rc;
-    if (ctx->desc[0].gauge == GF_LANDAU) {
-        // spectrum [t][a][z][y][kx]: the t axis of all 8 components in one call
-        int nt1[1] = {g.nt};
-        const int cols = (int)(8 * S);
-        if ((rc = make_plan(ctx->fft_t, 1, nt1, nt1, cols, 1, nt1, cols, 1, dp ? HIPFFT_Z2Z : HIPFFT_C2C, cols)))
-            return rc;
-    }
-    ctx->sd_ready = true;
-    return GF_OK;
-}
-
-int sd_t_transform(gf_ctx *ctx, int dir) {
-    if (ctx->prec == GF_F64) {
-        hipfftDoubleComplex *p = (hipfftDoubleComplex *)ctx->d_spec;
-        FFTTRY(ctx, hipfftExecZ2Z(ctx->fft_t, p, p, dir));
-    } else {
-        hipfftComplex *p = (hipfftComplex *)ctx->d_spec;
-        FFTTRY(ctx, hipfftExecC2C(ctx->fft_t, p, p, dir));
+        ctx->d_roots = w;
     }
     return GF_OK;
 }
 
+const void *sd_roots(const gf_ctx *ctx, int axis) {
+    return (const char *)ctx->d_roots + (size_t)axis * FFT_MAX_N * 16;
+}
+
+// One step of Alg. 2: Delta -> F (x, y, z and, for Landau, t) -> times
+// (alpha/2) p2max / p^2 / N -> F^-1 -> g = reunit(1 + X) -> U <- g U g^dagger.
+// The filter sits in the last forward pass (t for Landau, z for Coulomb),
+// between its forward and inverse transform.
 int sd_step_impl(gf_ctx *ctx, void *U, double alpha) {
-    int rc;
     const Geom &g = ctx->desc[0].g;
     const int gauge = ctx->desc[0].gauge;
     const bool landau = gauge == GF_LANDAU;
-    HIPTRY(ctx, launch_sd_delta(ctx->prec, ctx->nelem, gauge, g, U, ctx->d_sd, ctx->stream));
-    if (ctx->prec == GF_F64)
-        FFTTRY(ctx, hipfftExecD2Z(ctx->fft_fwd, (hipfftDoubleReal *)ctx->d_sd, (hipfftDoubleComplex *)ctx->d_spec));
-    else
-        FFTTRY(ctx, hipfftExecR2C(ctx->fft_fwd, (hipfftReal *)ctx->d_sd, (hipfftComplex *)ctx->d_spec));
-    if (landau && (rc = sd_t_transform(ctx, HIPFFT_FORWARD))) return rc;
+    const FftX fx = make_fft_x(g);
+    const FftAxis fy = make_fft_axis(g, 1, !landau);
+    const FftAxis fz = make_fft_axis(g, 2, !landau);
+    FftAxis flt = landau ? make_fft_axis(g, 3, false) : fz;
     const double nfft = landau ? (double)g.V : (double)g.nx * g.ny * g.nz;
-    const double p2max = landau ? 16.0 : 12.0;
-    HIPTRY(ctx, launch_sd_filter(ctx->prec, g, landau ? 1 : 0, ctx->d_spec, 0.5 * alpha / nfft, p2max, ctx->stream));
-    if (landau && (rc = sd_t_transform(ctx, HIPFFT_BACKWARD))) return rc;
-    if (ctx->prec == GF_F64)
-        FFTTRY(ctx, hipfftExecZ2D(ctx->fft_inv, (hipfftDoubleComplex *)ctx->d_spec, (hipfftDoubleReal *)ctx->d_sd));
-    else
-        FFTTRY(ctx, hipfftExecC2R(ctx->fft_inv, (hipfftComplex *)ctx->d_spec, (hipfftReal *)ctx->d_sd));
-    HIPTRY(ctx, launch_sd_gfield(ctx->prec, g, ctx->d_sd, ctx->d_gfield, ctx->stream));
-    HIPTRY(ctx, launch_gauge_transform(ctx->prec, ctx->nelem, g, U, ctx->d_gfield, ctx->stream));
+    flt.scale = 0.5 * alpha / nfft;
+    flt.p2max = landau ? 16.0 : 12.0;
+    hipStream_t st = ctx->stream;
+    HIPTRY(ctx, launch_sd_delta(ctx->prec, ctx->nelem, gauge, g, U, ctx->d_sd, st));
+    const void *wx = sd_roots(ctx, 0), *wy = sd_roots(ctx, 1), *wz = sd_roots(ctx, 2), *wt = sd_roots(ctx, 3);
+    HIPTRY(ctx, launch_fft_x(ctx->prec, fx, wx, ctx->d_sd, ctx->d_spec, 0, st));
+    HIPTRY(ctx, launch_fft_axis(ctx->prec, fy, wy, ctx->d_spec, -1, 0, st));
+    if (landau) HIPTRY(ctx, launch_fft_axis(ctx->prec, fz, wz, ctx->d_spec, -1, 0, st));
+    HIPTRY(ctx, launch_fft_axis(ctx->prec, flt, landau ? wt : wz, ctx->d_spec, -1, 1, st));
+    if (landau) HIPTRY(ctx, launch_fft_axis(ctx->prec, fz, wz, ctx->d_spec, 1, 0, st));
+    HIPTRY(ctx, launch_fft_axis(ctx->prec, fy, wy, ctx->d_spec, 1, 0, st));
+    HIPTRY(ctx, launch_fft_x(ctx->prec, fx, wx, ctx->d_sd, ctx->d_spec, 1, st));
+    HIPTRY(ctx, launch_sd_gfield(ctx->prec, g, ctx->d_sd, ctx->d_gfield, st));
+    HIPTRY(ctx, launch_gauge_transform(ctx->prec, ctx->nelem, g, U, ctx->d_gfield, st));
     return GF_OK;
 }
 

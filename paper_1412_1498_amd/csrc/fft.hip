@@ -1,0 +1,481 @@
+// fft.hip -- the lattice Fourier transforms of steepest descent with Fourier
+// acceleration (Alg. 2, eqs. 8-9) on gfx950.
+//
+// The eight real su(3) components of Delta are held as d[t][a][z][y][x]; their
+// spectrum as spec[t][a][z][y][kx] with kx = 0..nx/2 (the real transform along
+// x keeps half the spectrum, the other half being its complex conjugate). One
+// pass per axis: x (real <-> half complex), then y, z and t (complex, in place);
+// the multiplication by p2_max / p^2(k) is fused into the last forward pass,
+// between its forward and inverse transform, so that pass writes back the
+// filtered field already transformed back along its own axis.
+//
+// A workgroup loads a tile of pencils (for y, z, t: consecutive kx of one row,
+// so every global access is a contiguous run) into LDS and transforms them by
+// the mixed-radix Stockham algorithm (radix 4, 2, 3, 5 butterflies in
+// registers, any larger prime by a direct sum): one LDS read, one write and
+// one twiddle per point and pass, the passes alternating between two LDS
+// buffers. The arithmetic is in double for both link precisions (a double
+// FMA costs the same as a float one on this GPU); the spectrum is stored in
+// the context precision.
+#include "gf_internal.hpp"
+#include "su3_device.hpp"
+#include "tile_order.hpp"
+
+namespace gf {
+
+namespace {
+
+struct Cd {
+    double x, y;
+};
+
+__device__ __forceinline__ Cd cmul(Cd a, Cd b) {
+    Cd r;
+    r.x = fma(a.x, b.x, -a.y * b.y);
+    r.y = fma(a.x, b.y, a.y * b.x);
+    return r;
+}
+
+__device__ __forceinline__ void cmac(Cd &acc, Cd a, Cd b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+}
+
+// LDS of a transform tile: one buffer holding element j of pencil q at
+// a[j * ld + q] (ld >= np pencils; the x transforms pad it so that a pencil's
+// consecutive elements fall in different banks), transformed in place, and
+// the n roots exp(2 pi i m / n).
+struct Tile {
+    Cd *a, *Wl;
+    int ld;
+    FastDiv dnp;  // division by the pencil count
+};
+
+__host__ __device__ inline int tile_lds_points(int n, int ld) { return n * ld + n; }
+
+__device__ __forceinline__ Tile tile_setup(Cd *lds, const Cd *__restrict__ Wg, int n, int ld, const FastDiv &dnp) {
+    Tile t;
+    t.a = lds;
+    t.ld = ld;
+    t.dnp = dnp;
+    t.Wl = lds + n * ld;
+    for (int m = threadIdx.x; m < n; m += blockDim.x) t.Wl[m] = Wg[m];
+    return t;  // lds_dft begins with a barrier
+}
+
+// w or its conjugate: the table holds exp(+2 pi i m / n); SIGN = -1 forward.
+template <int SIGN>
+__device__ __forceinline__ Cd root(Cd w) {
+    if constexpr (SIGN < 0) w.y = -w.y;
+    return w;
+}
+
+__device__ __forceinline__ Cd cadd(Cd a, Cd b) { return Cd{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ Cd csub(Cd a, Cd b) { return Cd{a.x - b.x, a.y - b.y}; }
+// i s z for s = +-1
+template <int S>
+__device__ __forceinline__ Cd imul(Cd z) { return S > 0 ? Cd{-z.y, z.x} : Cd{z.y, -z.x}; }
+
+// In-register R-point DFTs, X_s = sum_m v_m exp(SIGN 2 pi i m s / R).
+template <int SIGN>
+__device__ __forceinline__ void bfly2(Cd *v) {
+    const Cd a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void bfly4(Cd *v) {
+    const Cd t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const Cd t2 = cadd(v[1], v[3]), t3 = imul<SIGN>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void bfly3(Cd *v) {
+    const double h = 0.86602540378443864676;  // sin(2 pi / 3)
+    const Cd s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    const Cd t = Cd{v[0].x - 0.5 * s.x, v[0].y - 0.5 * s.y};
+    const Cd u = imul<SIGN>(Cd{h * d.x, h * d.y});
+    v[0] = cadd(v[0], s);
+    v[1] = cadd(t, u);
+    v[2] = csub(t, u);
+}
+
+template <int SIGN>
+__device__ __forceinline__ void bfly5(Cd *v) {
+    const double c1 = 0.30901699437494742410, c2 = -0.80901699437494742410;  // cos(2 pi/5), cos(4 pi/5)
+    const double s1 = 0.95105651629515357212, s2 = 0.58778525229247312917;   // sin(2 pi/5), sin(4 pi/5)
+    const Cd a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const Cd a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const Cd p = Cd{v[0].x + c1 * a1.x + c2 * a2.x, v[0].y + c1 * a1.y + c2 * a2.y};
+    const Cd r = Cd{v[0].x + c2 * a1.x + c1 * a2.x, v[0].y + c2 * a1.y + c1 * a2.y};
+    const Cd u = imul<SIGN>(Cd{s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y});
+    const Cd w = imul<SIGN>(Cd{s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y});
+    v[0] = cadd(v[0], cadd(a1, a2));
+    v[1] = cadd(p, u);
+    v[4] = csub(p, u);
+    v[2] = cadd(r, w);
+    v[3] = csub(r, w);
+}
+
+// Butterflies per thread in a radix-R pass: a tile holds at most
+// FFT_TILE_POINTS points, i.e. FFT_TILE_POINTS / R butterflies, over
+// FFT_BLOCK threads; outputs per thread in a pass of any other radix.
+constexpr int pass_b(int R) { return (FFT_TILE_POINTS / R + FFT_BLOCK - 1) / FFT_BLOCK; }
+constexpr int PASS_OUT = (FFT_TILE_POINTS + FFT_BLOCK - 1) / FFT_BLOCK;
+
+// One radix-R pass of the Stockham autosort algorithm over np pencils (element
+// j of pencil q at [j * ld + q]), in place: Ns = product of the earlier
+// radices; butterfly j reads j + r n/R, twiddles by
+// exp(SIGN 2 pi i r (j mod Ns) / (Ns R)), and writes (j / Ns) Ns R + (j mod Ns) + r Ns.
+// Every thread reads all its butterflies into registers before the barrier
+// and writes them after it.
+template <int SIGN, int R>
+__device__ __forceinline__ void stockham_pass(Cd *buf, const Cd *Wl, int n, int Ns, int np, int ld,
+                                              const FastDiv &dnp, const FastDiv &dns) {
+    constexpr int B = pass_b(R);
+    const int nb = n / R, tw = n / (Ns * R), total = nb * np;
+    Cd v[B][R];
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+        const int bi = threadIdx.x + i * FFT_BLOCK;
+        if (bi < total) {
+            const int j = (int)fdiv((unsigned)bi, dnp), q = bi - j * np;
+            const int k = j - (int)fdiv((unsigned)j, dns) * Ns;
+#pragma unroll
+            for (int r = 0; r < R; r++) v[i][r] = buf[(j + r * nb) * ld + q];
+#pragma unroll
+            for (int r = 1; r < R; r++) v[i][r] = cmul(v[i][r], root<SIGN>(Wl[r * k * tw]));
+            if constexpr (R == 2) bfly2<SIGN>(v[i]);
+            if constexpr (R == 3) bfly3<SIGN>(v[i]);
+            if constexpr (R == 4) bfly4<SIGN>(v[i]);
+            if constexpr (R == 5) bfly5<SIGN>(v[i]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < B; i++) {
+        const int bi = threadIdx.x + i * FFT_BLOCK;
+        if (bi < total) {
+            const int j = (int)fdiv((unsigned)bi, dnp), q = bi - j * np;
+            const int jh = (int)fdiv((unsigned)j, dns), k = j - jh * Ns;
+            const int d = jh * Ns * R + k;
+#pragma unroll
+            for (int r = 0; r < R; r++) buf[(d + r * Ns) * ld + q] = v[i][r];
+        }
+    }
+}
+
+// A pass of any radix R (the primes above 5), in place: one output per
+// thread and slot, the R-point sum over the root table.
+template <int SIGN>
+__device__ __forceinline__ void stockham_pass_any(Cd *buf, const Cd *Wl, int n, int Ns, int R, int np, int ld) {
+    const int nb = n / R, tw = n / (Ns * R), nR = n / R, total = n * np;
+    Cd o[PASS_OUT];
+#pragma unroll
+    for (int i = 0; i < PASS_OUT; i++) {
+        const int idx = threadIdx.x + i * FFT_BLOCK;
+        if (idx < total) {
+            const int q = idx % np, rest = idx / np, j = rest % nb, s = rest / nb, k = j % Ns;
+            Cd acc = {0.0, 0.0};
+            for (int r = 0; r < R; r++) {
+                Cd x = buf[(j + r * nb) * ld + q];
+                if (r) x = cmul(x, root<SIGN>(Wl[r * k * tw]));
+                cmac(acc, x, root<SIGN>(Wl[((r * s) % R) * nR]));
+            }
+            o[i] = acc;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < PASS_OUT; i++) {
+        const int idx = threadIdx.x + i * FFT_BLOCK;
+        if (idx < total) {
+            const int q = idx % np, rest = idx / np, j = rest % nb, s = rest / nb, k = j % Ns;
+            buf[((j / Ns) * Ns * R + k + s * Ns) * ld + q] = o[i];
+        }
+    }
+}
+
+// DFT of np pencils of length n held in t.a, in place. Begins and ends with
+// a barrier.
+template <int SIGN>
+__device__ __forceinline__ void lds_dft(const Tile &t, const FftPlan &pl, int n, int np) {
+    int Ns = 1;
+    for (int f = 0; f < pl.nf; f++) {
+        __syncthreads();
+        const int R = pl.fac[f];
+        if (R == 4) stockham_pass<SIGN, 4>(t.a, t.Wl, n, Ns, np, t.ld, t.dnp, pl.ns[f]);
+        else if (R == 2) stockham_pass<SIGN, 2>(t.a, t.Wl, n, Ns, np, t.ld, t.dnp, pl.ns[f]);
+        else if (R == 3) stockham_pass<SIGN, 3>(t.a, t.Wl, n, Ns, np, t.ld, t.dnp, pl.ns[f]);
+        else if (R == 5) stockham_pass<SIGN, 5>(t.a, t.Wl, n, Ns, np, t.ld, t.dnp, pl.ns[f]);
+        else stockham_pass_any<SIGN>(t.a, t.Wl, n, Ns, R, np, t.ld);
+        Ns *= R;
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ double lattice_p2(int k, int L) {
+    if (L <= 0) return 0.0;
+    const double s = sinpi((double)k / (double)L);
+    return 4.0 * s * s;
+}
+
+}  // namespace
+
+// Forward real transform along x: rows of nx reals -> nkx complex. Two real
+// rows a, b go through one complex transform of z = a + i b:
+// A[k] = (Z[k] + conj Z[-k]) / 2, B[k] = (Z[k] - conj Z[-k]) / 2i.
+template <typename R>
+__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) k_fft_rx_fwd(FftX f, const Cd *__restrict__ Wg, const R *__restrict__ d,
+                                                          typename V2<R>::type *__restrict__ spec) {
+    extern __shared__ Cd lds[];
+    const int nc = f.nr / 2, nx = f.n;  // complex rows per workgroup
+    const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
+    const long long row0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.nr;
+    for (int idx = threadIdx.x; idx < f.nr * nx; idx += blockDim.x) {
+        const int r = (int)fdiv((unsigned)idx, f.dn), j = idx - r * nx;
+        const double v = row0 + r < f.rows ? (double)d[(row0 + r) * nx + j] : 0.0;
+        Cd &z = t.a[j * t.ld + (r >> 1)];
+        if (r & 1) z.y = v; else z.x = v;
+    }
+    lds_dft<-1>(t, f.pl, nx, nc);
+    const Cd *Z = t.a;
+    for (int idx = threadIdx.x; idx < f.nr * f.nkx; idx += blockDim.x) {
+        const int r = (int)fdiv((unsigned)idx, f.dnkx), k = idx - r * f.nkx;
+        if (row0 + r < f.rows) {
+            const Cd zk = Z[k * t.ld + (r >> 1)], zm = Z[((nx - k) % nx) * t.ld + (r >> 1)];
+            typename V2<R>::type v;
+            if (r & 1) {  // (zk - conj zm) / 2i
+                v.x = (R)(0.5 * (zk.y + zm.y));
+                v.y = (R)(-0.5 * (zk.x - zm.x));
+            } else {      // (zk + conj zm) / 2
+                v.x = (R)(0.5 * (zk.x + zm.x));
+                v.y = (R)(0.5 * (zk.y - zm.y));
+            }
+            spec[(row0 + r) * f.nkx + k] = v;
+        }
+    }
+}
+
+// Inverse real transform along x: nkx complex per row (the rest by conjugate
+// symmetry; the imaginary parts at kx = 0 and nx/2 are dropped, as for any
+// real inverse transform) -> nx reals, unnormalised. Rows a, b travel as
+// Z = A + i B, whose inverse is a + i b: frequency k of the pair gives
+// Z[k] = A + i B and Z[nx - k] = conj A + i conj B.
+template <typename R>
+__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) k_fft_rx_inv(FftX f, const Cd *__restrict__ Wg,
+                                                          const typename V2<R>::type *__restrict__ spec,
+                                                          R *__restrict__ d) {
+    extern __shared__ Cd lds[];
+    const int nc = f.nr / 2, nx = f.n, h = nx / 2;
+    const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
+    const long long row0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.nr;
+    for (int idx = threadIdx.x; idx < nc * f.nkx; idx += blockDim.x) {
+        const int c = (int)fdiv((unsigned)idx, f.dnkx), k = idx - c * f.nkx;
+        Cd A = {0.0, 0.0}, B = {0.0, 0.0};
+        if (row0 + 2 * c < f.rows) {
+            const typename V2<R>::type va = spec[(row0 + 2 * c) * f.nkx + k];
+            const typename V2<R>::type vb = spec[(row0 + 2 * c + 1) * f.nkx + k];
+            A = Cd{(double)va.x, (double)va.y};
+            B = Cd{(double)vb.x, (double)vb.y};
+        }
+        if (k == 0 || k == h) {
+            t.a[k * t.ld + c] = Cd{A.x, B.x};
+        } else {
+            t.a[k * t.ld + c] = Cd{A.x - B.y, A.y + B.x};
+            t.a[(nx - k) * t.ld + c] = Cd{A.x + B.y, B.x - A.y};
+        }
+    }
+    lds_dft<1>(t, f.pl, nx, nc);
+    for (int idx = threadIdx.x; idx < f.nr * nx; idx += blockDim.x) {
+        const int r = (int)fdiv((unsigned)idx, f.dn), j = idx - r * nx;
+        if (row0 + r < f.rows) {
+            const Cd v = t.a[j * t.ld + (r >> 1)];
+            d[(row0 + r) * nx + j] = (R)((r & 1) ? v.y : v.x);
+        }
+    }
+}
+
+// Complex transform along one of y, z, t, in place. A workgroup takes np
+// consecutive kx of one row (outer index = the other three of t, a, z, y).
+// FILTER: forward transform, multiply by scale p2max / p^2(k) (0 at p^2 = 0),
+// inverse transform.
+template <typename R, bool FILTER>
+__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) k_fft_axis(FftAxis f, const Cd *__restrict__ Wg,
+                                                        typename V2<R>::type *__restrict__ spec, int sign) {
+    extern __shared__ Cd lds[];
+    const int n = f.n, np = f.np;
+    const Tile t = tile_setup(lds, Wg, n, np, f.dnp);
+    // XCD-contiguous tile order: neighbouring tiles (the kx chunks of a row,
+    // then the next row) share cache lines and meet in one L2
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int chunk = tile % f.nchunk;
+    int o = tile / f.nchunk;
+    const int d0 = o % f.r[0];
+    o /= f.r[0];
+    const int d1 = o % f.r[1], d2 = o / f.r[1];
+    const int kx0 = chunk * np;
+    const long long base = d0 * f.s[0] + d1 * f.s[1] + d2 * f.s[2] + kx0;
+    for (int idx = threadIdx.x; idx < n * np; idx += blockDim.x) {
+        const int j = (int)fdiv((unsigned)idx, f.dnp), q = idx - j * np;
+        Cd v = {0.0, 0.0};
+        if (kx0 + q < f.nkx) {
+            const typename V2<R>::type s = spec[base + j * f.s_ax + q];
+            v.x = (double)s.x;
+            v.y = (double)s.y;
+        }
+        t.a[idx] = v;
+    }
+    if (FILTER || sign < 0) lds_dft<-1>(t, f.pl, n, np);
+    else lds_dft<1>(t, f.pl, n, np);
+    Cd *res = t.a;
+    if constexpr (FILTER) {
+        // 4 sin^2(pi k / L) of this axis and of the tile's kx, once per workgroup
+        double *p2ax = (double *)(t.Wl + n), *p2x = p2ax + n;
+        for (int m = threadIdx.x; m < n + np; m += blockDim.x) {
+            if (m < n) p2ax[m] = lattice_p2(m, f.Lax);
+            else p2x[m - n] = lattice_p2(kx0 + m - n, f.Lx);
+        }
+        __syncthreads();
+        const double p2o = lattice_p2(d0, f.L[0]) + lattice_p2(d1, f.L[1]) + lattice_p2(d2, f.L[2]);
+        const double sp = f.scale * f.p2max;
+        for (int idx = threadIdx.x; idx < n * np; idx += blockDim.x) {
+            const int k = (int)fdiv((unsigned)idx, f.dnp), q = idx - k * np;
+            const double p2 = p2o + p2ax[k] + p2x[q];
+            const double fac = p2 > 0.0 ? sp / p2 : 0.0;
+            res[idx].x *= fac;
+            res[idx].y *= fac;
+        }
+        lds_dft<1>(t, f.pl, n, np);  // back along the same axis
+    }
+    for (int idx = threadIdx.x; idx < n * np; idx += blockDim.x) {
+        const int j = (int)fdiv((unsigned)idx, f.dnp), q = idx - j * np;
+        if (kx0 + q < f.nkx) {
+            typename V2<R>::type v;
+            v.x = (R)res[idx].x;
+            v.y = (R)res[idx].y;
+            spec[base + j * f.s_ax + q] = v;
+        }
+    }
+}
+
+// W[m] = exp(2 pi i m / n), m < n.
+__global__ void __launch_bounds__(256) k_fft_roots(Cd *__restrict__ W, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double s, c;
+    sincospi(2.0 * (double)m / (double)n, &s, &c);
+    W[m] = Cd{c, s};
+}
+
+// Radices of a length: 4s first, then 2, 3, 5, then any other primes.
+static FftPlan plan_length(int n) {
+    FftPlan p{};
+    int ns = 1;
+    auto push = [&](int r) { p.ns[p.nf] = make_fastdiv((unsigned)ns); p.fac[p.nf++] = r; ns *= r; };
+    while (n % 4 == 0) { push(4); n /= 4; }
+    for (int r : {2, 3, 5})
+        while (n % r == 0) { push(r); n /= r; }
+    for (int r = 7; n > 1; r += 2)
+        while (n % r == 0) { push(r); n /= r; }
+    return p;
+}
+
+FftX make_fft_x(const Geom &g) {
+    FftX f;
+    f.n = g.nx;
+    f.nkx = g.nx / 2 + 1;
+    f.pl = plan_length(f.n);
+    const int nc = FFT_TILE_POINTS / g.nx > 0 ? FFT_TILE_POINTS / g.nx : 1;  // complex rows
+    f.nr = 2 * nc;
+    f.rows = (long long)g.nt * 8 * g.nz * g.ny;
+    f.dn = make_fastdiv((unsigned)f.n);
+    f.dnkx = make_fastdiv((unsigned)f.nkx);
+    f.dnc = make_fastdiv((unsigned)nc);
+    return f;
+}
+
+// axis: 1 = y, 2 = z, 3 = t. spec strides: kx 1, y nkx, z ny nkx, a nz ny nkx, t 8 nz ny nkx.
+FftAxis make_fft_axis(const Geom &g, int axis, bool coulomb) {
+    FftAxis f{};
+    const long long nkx = g.nx / 2 + 1, sy = nkx, sz = g.ny * sy, sa = g.nz * sz, st = 8 * sa;
+    f.nkx = (int)nkx;
+    f.Lx = g.nx;
+    if (axis == 1) {
+        f.n = g.ny; f.s_ax = sy;
+        f.r[0] = g.nz; f.s[0] = sz; f.L[0] = g.nz;
+        f.r[1] = 8;    f.s[1] = sa; f.L[1] = 0;
+        f.r[2] = g.nt; f.s[2] = st; f.L[2] = coulomb ? 0 : g.nt;
+    } else if (axis == 2) {
+        f.n = g.nz; f.s_ax = sz;
+        f.r[0] = g.ny; f.s[0] = sy; f.L[0] = g.ny;
+        f.r[1] = 8;    f.s[1] = sa; f.L[1] = 0;
+        f.r[2] = g.nt; f.s[2] = st; f.L[2] = coulomb ? 0 : g.nt;
+    } else {
+        f.n = g.nt; f.s_ax = st;
+        f.r[0] = g.ny; f.s[0] = sy; f.L[0] = g.ny;
+        f.r[1] = g.nz; f.s[1] = sz; f.L[1] = g.nz;
+        f.r[2] = 8;    f.s[2] = sa; f.L[2] = 0;
+    }
+    f.Lax = f.n;
+    f.pl = plan_length(f.n);
+    // kx chunks of at most FFT_TILE_POINTS / n, as even as possible
+    const int cap = FFT_TILE_POINTS / f.n > 0 ? FFT_TILE_POINTS / f.n : 1;
+    f.nchunk = (f.nkx + cap - 1) / cap;
+    f.np = (f.nkx + f.nchunk - 1) / f.nchunk;
+    f.dnp = make_fastdiv((unsigned)f.np);
+    return f;
+}
+
+static size_t lds_bytes(int n, int np) { return (size_t)tile_lds_points(n, np) * sizeof(Cd); }
+
+hipError_t launch_fft_roots(void *W, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_fft_roots, dim3((n + 255) / 256), dim3(256), 0, st, (Cd *)W, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_x(int prec, const FftX &f, const void *W, void *d, void *spec, int inverse, hipStream_t st) {
+    const dim3 grid((unsigned)((f.rows + f.nr - 1) / f.nr));
+    const size_t sh = lds_bytes(f.n, f.nr / 2 + 1);
+    const Cd *w = (const Cd *)W;
+    if (prec == 0) {
+        if (inverse)
+            hipLaunchKernelGGL(k_fft_rx_inv<double>, grid, dim3(FFT_BLOCK), sh, st, f, w,
+                               (const V2<double>::type *)spec, (double *)d);
+        else
+            hipLaunchKernelGGL(k_fft_rx_fwd<double>, grid, dim3(FFT_BLOCK), sh, st, f, w, (const double *)d,
+                               (V2<double>::type *)spec);
+    } else {
+        if (inverse)
+            hipLaunchKernelGGL(k_fft_rx_inv<float>, grid, dim3(FFT_BLOCK), sh, st, f, w,
+                               (const V2<float>::type *)spec, (float *)d);
+        else
+            hipLaunchKernelGGL(k_fft_rx_fwd<float>, grid, dim3(FFT_BLOCK), sh, st, f, w, (const float *)d,
+                               (V2<float>::type *)spec);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fft_axis(int prec, const FftAxis &f, const void *W, void *spec, int sign, int filter,
+                           hipStream_t st) {
+    const dim3 grid((unsigned)((long long)f.r[0] * f.r[1] * f.r[2] * f.nchunk));
+    // the filter's tables of the axis and kx terms (n + np doubles) follow the roots
+    const size_t sh = lds_bytes(f.n, f.np) + (filter ? (size_t)(f.n + f.np) * sizeof(double) : 0);
+    const Cd *w = (const Cd *)W;
+    const int sg = sign < 0 ? -1 : 1;
+#define GF_L(R, FL) \
+    hipLaunchKernelGGL((k_fft_axis<R, FL>), grid, dim3(FFT_BLOCK), sh, st, f, w, (V2<R>::type *)spec, sg)
+    if (prec == 0) { if (filter) GF_L(double, true); else GF_L(double, false); }
+    else { if (filter) GF_L(float, true); else GF_L(float, false); }
+#undef GF_L
+    return hipGetLastError();
+}
+
+}  // namespace gf

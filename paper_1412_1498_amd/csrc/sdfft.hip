@@ -1,9 +1,9 @@
 // sdfft.hip -- kernels of steepest descent with Fourier acceleration
 // (Alg. 2, eqs. 7-9): the divergence Delta(x) as 8 real su(3) components in
-// lexicographic site order (the FFT input), the p^2_max / p^2 filter applied
-// in momentum space, and the first-order gauge transformation
-// g(x) = reunit(1 + (alpha/2) F^-1[...] Delta) written as a g field for
-// k_gauge_transform. The FFTs themselves are hipFFT calls made by the host.
+// lexicographic site order (the input of the transforms in fft.hip, which
+// also apply the p^2_max / p^2 filter), and the first-order gauge
+// transformation g(x) = reunit(1 + (alpha/2) F^-1[...] Delta) written as a g
+// field for k_gauge_transform.
 //
 // Delta is anti-hermitian and traceless: Delta = i sum_a d_a lambda_a with
 // d_a = Tr[lambda_a Delta] / (2i) real, so filtering the eight real d_a is
@@ -78,43 +78,11 @@ __global__ void __launch_bounds__(SD_TILE) k_sd_delta(Geom g, int nd, const type
     o[6] = 0.5 * (ar[5] - ar[7]);
     o[7] = 0.5 * r3 * (ai[0] + ai[4] - 2.0 * ai[8]);
     const int lx = lex_of(g, p, h);
-    // layout [t][a][z][y][x]: one hipFFT call then covers the t axis of all components
+    // layout [t][a][z][y][x]: rows along x for the real transform
     const int V3 = g.V / g.nt;
     const int t = lx / V3, x3 = lx - t * V3;
 #pragma unroll
     for (int a = 0; a < 8; a++) d[((long long)t * 8 + a) * V3 + x3] = (R)o[a];
-}
-
-// Spectrum layout [t][a][z][y][kx], kx = 0..nx/2 (half spectrum of the real
-// transform along x). Multiply by scale * p2max / p^2(k), zero mode -> 0.
-// One thread per mode: the factor is computed once and applied to the eight
-// components.
-template <typename C>
-__global__ void __launch_bounds__(256) k_sd_filter(Geom g, int with_t, C *__restrict__ spec, double scale, double p2max) {
-    const int nkx = g.nx / 2 + 1;
-    const long long S = (long long)g.nz * g.ny * nkx;
-    const long long per = (long long)g.nt * S;
-    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= per) return;
-    long long r = i;
-    const int kx = (int)(r % nkx); r /= nkx;
-    const int ky = (int)(r % g.ny); r /= g.ny;
-    const int kz = (int)(r % g.nz); r /= g.nz;
-    const int kt = (int)r;
-    double p2 = 0.0, s;
-    s = sinpi((double)kx / g.nx); p2 += 4.0 * s * s;
-    s = sinpi((double)ky / g.ny); p2 += 4.0 * s * s;
-    s = sinpi((double)kz / g.nz); p2 += 4.0 * s * s;
-    if (with_t) { s = sinpi((double)kt / g.nt); p2 += 4.0 * s * s; }
-    const double f = p2 > 0.0 ? scale * p2max / p2 : 0.0;
-    const long long base = (long long)kt * 8 * S + (i - (long long)kt * S);
-#pragma unroll
-    for (int a = 0; a < 8; a++) {
-        C v = spec[base + a * S];
-        v.x = (decltype(v.x))(v.x * f);
-        v.y = (decltype(v.y))(v.y * f);
-        spec[base + a * S] = v;
-    }
 }
 
 // g(x) = reunit(1 + i sum_a d_a lambda_a) in double, stored as the g field
@@ -173,20 +141,6 @@ hipError_t launch_sd_delta(int prec, int nelem, int gauge, const Geom &g, const 
     if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
     else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L
-    return hipGetLastError();
-}
-
-hipError_t launch_sd_filter(int prec, const Geom &g, int with_t, void *spec, double scale,
-                            double p2max, hipStream_t st) {
-    const long long n = (long long)g.nt * g.nz * g.ny * (g.nx / 2 + 1);
-    const int B = 256;
-    const dim3 grid((unsigned)((n + B - 1) / B));
-    if (prec == 0)
-        hipLaunchKernelGGL(k_sd_filter<double2>, grid, dim3(B), 0, st, g, with_t, (double2 *)spec,
-                           scale, p2max);
-    else
-        hipLaunchKernelGGL(k_sd_filter<float2>, grid, dim3(B), 0, st, g, with_t, (float2 *)spec,
-                           scale, p2max);
     return hipGetLastError();
 }
 

@@ -3,8 +3,10 @@ the FP64 oracle (oracle/sdfft.py), through the C ABI.
 
 Tolerances: FP64 links after one step 1e-13 abs (the oracle transforms the
 nine complex matrix elements with numpy's FFT, the GPU the eight real su(3)
-components with hipFFT: same linear map, different rounding); FP32 5e-6
-(float FFTs and float g)."""
+components with its own two-level DFT passes: same linear map, different
+rounding); FP32 5e-6 (a float spectrum between the passes and a float g).
+The lattice extents include odd factors (6 = 3 2, 10 = 5 2, 12 = 4 3,
+14 = 7 2) and the smallest, 2."""
 import numpy as np
 import pytest
 import torch
@@ -35,7 +37,7 @@ def host(ctx, Ug):
 
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
-@pytest.mark.parametrize("dims", [(4, 6, 2, 8), (8, 8, 8, 8), (6, 4, 4, 2)])
+@pytest.mark.parametrize("dims", [(4, 6, 2, 8), (8, 8, 8, 8), (6, 4, 4, 2), (10, 6, 12, 14), (2, 4, 2, 6)])
 def test_sd_step_matches_oracle(gf, field_cache, prec, gauge, dims):
     U = field_cache(dims, 0.4, 70)
     ctx, Ug = setup(gf, dims, gauge, prec, U)
@@ -79,3 +81,13 @@ def test_sd_rejects_bad_alpha(gf, field_cache):
         with pytest.raises(gf.GFError) as e:
             ctx.sd_step(Ug, a)
         assert e.value.code == gf.EINVAL
+
+
+def test_sd_rejects_extents_beyond_the_transform_tile(gf):
+    """An extent above 1024 does not fit one transform tile: refused before
+    any kernel runs."""
+    ctx = gf.Context((1026, 2, 2, 2), gauge=LANDAU, prec=1)
+    U = ctx.empty_field()
+    with pytest.raises(gf.GFError) as e:
+        ctx.sd_step(U, 0.08)
+    assert e.value.code == gf.EUNSUPPORTED
