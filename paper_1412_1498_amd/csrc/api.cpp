@@ -18,6 +18,7 @@
 
 #include "gf.h"
 #include "gf_internal.hpp"
+#include "fft.hpp"
 #include "gf_math.hpp"
 #include "link8.hpp"
 #include "sun_internal.hpp"

@@ -17,7 +17,7 @@
 // buffers. The arithmetic is in double for both link precisions (a double
 // FMA costs the same as a float one on this GPU); the spectrum is stored in
 // the context precision.
-#include "gf_internal.hpp"
+#include "fft.hpp"
 #include "su3_device.hpp"
 #include "tile_order.hpp"
 
