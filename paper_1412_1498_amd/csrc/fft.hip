@@ -129,6 +129,11 @@ __device__ __forceinline__ void bfly5(Cd *v) {
 // FFT_BLOCK threads; outputs per thread in a pass of any other radix.
 constexpr int pass_b(int R) { return (FFT_TILE_POINTS / R + FFT_BLOCK - 1) / FFT_BLOCK; }
 constexpr int PASS_OUT = (FFT_TILE_POINTS + FFT_BLOCK - 1) / FFT_BLOCK;
+// Global loads per thread when a tile is filled (all issued before the first
+// use, so a workgroup waits for one memory latency, not one per element):
+// complex points of an axis tile; real elements of an x tile (2 per point).
+constexpr int LOAD_C = (FFT_TILE_POINTS + FFT_BLOCK - 1) / FFT_BLOCK;
+constexpr int LOAD_R = (2 * FFT_TILE_POINTS + FFT_BLOCK - 1) / FFT_BLOCK;
 
 // One radix-R pass of the Stockham autosort algorithm over np pencils (element
 // j of pencil q at [j * ld + q]), in place: Ns = product of the earlier
@@ -239,11 +244,23 @@ __global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(
     const int nc = f.nr / 2, nx = f.n;  // complex rows per workgroup
     const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
     const long long row0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.nr;
-    for (int idx = threadIdx.x; idx < f.nr * nx; idx += blockDim.x) {
-        const int r = (int)fdiv((unsigned)idx, f.dn), j = idx - r * nx;
-        const double v = row0 + r < f.rows ? (double)d[(row0 + r) * nx + j] : 0.0;
-        Cd &z = t.a[j * t.ld + (r >> 1)];
-        if (r & 1) z.y = v; else z.x = v;
+    {
+        const long long lim = (f.rows - row0 < f.nr ? f.rows - row0 : f.nr) * nx;  // elements of this tile
+        R v[LOAD_R];
+#pragma unroll
+        for (int i = 0; i < LOAD_R; i++) {
+            const int idx = threadIdx.x + i * FFT_BLOCK;
+            v[i] = idx < lim ? d[row0 * nx + idx] : (R)0;
+        }
+#pragma unroll
+        for (int i = 0; i < LOAD_R; i++) {
+            const int idx = threadIdx.x + i * FFT_BLOCK;
+            if (idx < f.nr * nx) {
+                const int r = (int)fdiv((unsigned)idx, f.dn), j = idx - r * nx;
+                Cd &z = t.a[j * t.ld + (r >> 1)];
+                if (r & 1) z.y = (double)v[i]; else z.x = (double)v[i];
+            }
+        }
     }
     lds_dft<-1>(t, f.pl, nx, nc);
     const Cd *Z = t.a;
@@ -277,15 +294,25 @@ __global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(
     const int nc = f.nr / 2, nx = f.n, h = nx / 2;
     const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
     const long long row0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.nr;
-    for (int idx = threadIdx.x; idx < nc * f.nkx; idx += blockDim.x) {
-        const int c = (int)fdiv((unsigned)idx, f.dnkx), k = idx - c * f.nkx;
-        Cd A = {0.0, 0.0}, B = {0.0, 0.0};
-        if (row0 + 2 * c < f.rows) {
-            const typename V2<R>::type va = spec[(row0 + 2 * c) * f.nkx + k];
-            const typename V2<R>::type vb = spec[(row0 + 2 * c + 1) * f.nkx + k];
-            A = Cd{(double)va.x, (double)va.y};
-            B = Cd{(double)vb.x, (double)vb.y};
+    typename V2<R>::type va[LOAD_C], vb[LOAD_C];
+#pragma unroll
+    for (int i = 0; i < LOAD_C; i++) {
+        const int idx = threadIdx.x + i * FFT_BLOCK;
+        va[i].x = va[i].y = vb[i].x = vb[i].y = (R)0;
+        if (idx < nc * f.nkx) {
+            const int c = (int)fdiv((unsigned)idx, f.dnkx), k = idx - c * f.nkx;
+            if (row0 + 2 * c < f.rows) {
+                va[i] = spec[(row0 + 2 * c) * f.nkx + k];
+                vb[i] = spec[(row0 + 2 * c + 1) * f.nkx + k];
+            }
         }
+    }
+#pragma unroll
+    for (int i = 0; i < LOAD_C; i++) {
+        const int idx = threadIdx.x + i * FFT_BLOCK;
+        if (idx >= nc * f.nkx) continue;
+        const int c = (int)fdiv((unsigned)idx, f.dnkx), k = idx - c * f.nkx;
+        const Cd A = Cd{(double)va[i].x, (double)va[i].y}, B = Cd{(double)vb[i].x, (double)vb[i].y};
         if (k == 0 || k == h) {
             t.a[k * t.ld + c] = Cd{A.x, B.x};
         } else {
@@ -323,15 +350,22 @@ __global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(
     const int d1 = o % f.r[1], d2 = o / f.r[1];
     const int kx0 = chunk * np;
     const long long base = d0 * f.s[0] + d1 * f.s[1] + d2 * f.s[2] + kx0;
-    for (int idx = threadIdx.x; idx < n * np; idx += blockDim.x) {
-        const int j = (int)fdiv((unsigned)idx, f.dnp), q = idx - j * np;
-        Cd v = {0.0, 0.0};
-        if (kx0 + q < f.nkx) {
-            const typename V2<R>::type s = spec[base + j * f.s_ax + q];
-            v.x = (double)s.x;
-            v.y = (double)s.y;
+    {
+        typename V2<R>::type v[LOAD_C];
+#pragma unroll
+        for (int i = 0; i < LOAD_C; i++) {
+            const int idx = threadIdx.x + i * FFT_BLOCK;
+            v[i].x = v[i].y = (R)0;
+            if (idx < n * np) {
+                const int j = (int)fdiv((unsigned)idx, f.dnp), q = idx - j * np;
+                if (kx0 + q < f.nkx) v[i] = spec[base + j * f.s_ax + q];
+            }
         }
-        t.a[idx] = v;
+#pragma unroll
+        for (int i = 0; i < LOAD_C; i++) {
+            const int idx = threadIdx.x + i * FFT_BLOCK;
+            if (idx < n * np) t.a[idx] = Cd{(double)v[i].x, (double)v[i].y};
+        }
     }
     if (FILTER || sign < 0) lds_dft<-1>(t, f.pl, n, np);
     else lds_dft<1>(t, f.pl, n, np);
