@@ -48,6 +48,46 @@ def test_sd_step_matches_oracle(gf, field_cache, prec, gauge, dims):
     assert np.abs(host(ctx, Ug) - Uo).max() < (1e-13 if prec == 0 else 5e-6)
 
 
+def filter_gain(dims, gauge):
+    """Largest factor p2max / p^2 the acceleration applies (at the lowest
+    nonzero momentum of the longest transformed axis). Rounding differences
+    between two transforms of Delta reach X multiplied by it, so a tolerance
+    set on lattices of extent <= 14 (gain < 100) scales with gain / 100."""
+    axes = dims[:3] if gauge == COULOMB else dims
+    p2max = 12.0 if gauge == COULOMB else 16.0
+    p2min = min(4 * np.sin(np.pi / L) ** 2 for L in axes)
+    return p2max / p2min
+
+
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("dims", [(1024, 2, 2, 2), (2, 1018, 2, 2), (2, 2, 1022, 2), (2, 2, 2, 1000)])
+def test_sd_step_long_axes(gf, field_cache, gauge, dims):
+    """One long axis, FP64: tiles at their size limit (1024 = 4^5, one pencil
+    per workgroup), the direct-sum pass of large prime factors (1018 = 2 509,
+    1022 = 2 7 73) and radix 5 (1000 = 4 2 5 5 5)."""
+    U = field_cache(dims, 0.4, 72)
+    ctx, Ug = setup(gf, dims, gauge, 0, U)
+    ctx.sd_step(Ug, 0.08)
+    Uo = sdfft.sd_step(U.copy(), 0.08, gauge)
+    tol = 1e-13 * max(1.0, filter_gain(dims, gauge) / 100)
+    assert np.abs(host(ctx, Ug) - Uo).max() < tol
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("dims", [(46, 2, 2, 2), (2, 34, 2, 2), (2, 2, 26, 2), (2, 2, 2, 22)])
+def test_sd_step_prime_factors(gf, field_cache, prec, gauge, dims):
+    """Axes with a prime factor above 5 (46 = 2 23, 34 = 2 17, 26 = 2 13,
+    22 = 2 11): the direct-sum pass, in both precisions."""
+    U = field_cache(dims, 0.4, 73)
+    ctx, Ug = setup(gf, dims, gauge, prec, U)
+    Uo = U.astype(np.complex64).astype(np.complex128) if prec == 1 else U.copy()
+    ctx.sd_step(Ug, 0.08)
+    Uo = sdfft.sd_step(Uo, 0.08, gauge)
+    tol = (1e-13 if prec == 0 else 5e-6) * max(1.0, filter_gain(dims, gauge) / 100)
+    assert np.abs(host(ctx, Ug) - Uo).max() < tol
+
+
 @pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
 def test_sd_fix_matches_oracle(gf, oracle_lib, field_cache, gauge):
     dims = (8, 8, 8, 8)
