@@ -100,3 +100,41 @@ def test_sd_steps(gf, field_cache, storage, prec, gauge):
         ctx.sd_step(Ug, 0.08)
         check_links(host(ctx, Ug), sdfft.sd_step(cur, 0.08, gauge), prec, storage,
                     1e-13 if prec == 0 else 5e-6)
+
+
+def test_full_size_48_fp32_12real_sampled_sites(gf, oracle_lib):
+    """48^4, amp 0.7, FP32 12-real links, the bench's default schedule: F and
+    theta of the whole field (row 2 rebuilt) equal the oracle's (F 1e-11
+    absolute, theta 1e-10 relative: the oracle's sequential sums); after one
+    even half-sweep the eight links of 128 sampled even sites equal the
+    oracle's single-site update of the same links, within the FP32 sweep
+    tolerance plus the rebuilt row's rounding (8 u)."""
+    from paper_1412_1498_amd import synth
+    dims = (48, 48, 48, 48)
+    U = synth.random_gauge_field(dims, 0.7, 0, device="cuda").to(torch.complex64)
+    ctx = gf.Context(dims, gauge=LANDAU, prec=1, params=gf.default_params(1, storage=1))
+    Ug = ctx.pack(U)
+    del U
+    Uo = host(ctx, Ug)
+    F0, th0 = ctx.quality(Ug)
+    Fo, tho = oracle_lib.quality(Uo, dims, LANDAU)
+    assert abs(F0 - Fo) <= 1e-11 and abs(th0 - tho) <= 1e-10 * tho
+    ctx.sweep(Ug, 0, 1.7)
+    back = host(ctx, Ug).reshape(-1, 4, 3, 3)
+    V = 48 ** 4
+    par = oracle_lib.parity_of_sites(dims)
+    rng = np.random.default_rng(0)
+    sites = [int(s) for s in rng.choice(V, 400, replace=False) if par[s] == 0][:128]
+    for s in sites:
+        oracle_lib.site_update(Uo, dims, s, 1.7)
+    O = Uo.reshape(-1, 4, 3, 3)
+    got, ref = [], []
+    for s in sites:
+        x, y, z, t = s % 48, (s // 48) % 48, (s // 48 ** 2) % 48, s // 48 ** 3
+        idx = [(s, mu) for mu in range(4)]
+        for mu, (c, step) in enumerate(zip((x, y, z, t), (1, 48, 48 ** 2, 48 ** 3))):
+            idx.append((s - step if c > 0 else s + 47 * step, mu))
+        for i, mu in idx:
+            got.append(back[i, mu])
+            ref.append(O[i, mu])
+    check_links(np.array(got), np.array(ref), 1, 1, 5e-6)
