@@ -12,11 +12,10 @@
 // A workgroup loads a tile of pencils (for y, z, t: consecutive kx of one row,
 // so every global access is a contiguous run) into LDS and transforms them by
 // the mixed-radix Stockham algorithm (radix 4, 2, 3, 5 butterflies in
-// registers, any larger prime by a direct sum): one LDS read, one write and
-// one twiddle per point and pass, the passes alternating between two LDS
-// buffers. The arithmetic is in double for both link precisions (a double
-// FMA costs the same as a float one on this GPU); the spectrum is stored in
-// the context precision.
+// registers, any larger prime by a direct sum), in place: one LDS read, one
+// write and one twiddle per point and pass. The arithmetic is in double for
+// both link precisions (a double FMA costs the same as a float one on this
+// GPU); the spectrum is stored in the context precision between passes.
 #include "fft.hpp"
 #include "su3_device.hpp"
 #include "tile_order.hpp"
@@ -234,12 +233,16 @@ __device__ __forceinline__ double lattice_p2(int k, int L) {
 
 }  // namespace
 
+// The transform kernels ask for four waves per SIMD (at most 128 VGPRs): a
+// pass's butterflies fit in that without spilling, and a CU then holds four
+// workgroups to overlap one tile's memory phase with another's passes.
+
 // Forward real transform along x: rows of nx reals -> nkx complex. Two real
 // rows a, b go through one complex transform of z = a + i b:
 // A[k] = (Z[k] + conj Z[-k]) / 2, B[k] = (Z[k] - conj Z[-k]) / 2i.
 template <typename R>
-__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) k_fft_rx_fwd(FftX f, const Cd *__restrict__ Wg, const R *__restrict__ d,
-                                                          typename V2<R>::type *__restrict__ spec) {
+__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_fft_rx_fwd(FftX f, const Cd *__restrict__ Wg, const R *__restrict__ d, typename V2<R>::type *__restrict__ spec) {
     extern __shared__ Cd lds[];
     const int nc = f.nr / 2, nx = f.n;  // complex rows per workgroup
     const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
@@ -287,9 +290,8 @@ __global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(
 // Z = A + i B, whose inverse is a + i b: frequency k of the pair gives
 // Z[k] = A + i B and Z[nx - k] = conj A + i conj B.
 template <typename R>
-__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) k_fft_rx_inv(FftX f, const Cd *__restrict__ Wg,
-                                                          const typename V2<R>::type *__restrict__ spec,
-                                                          R *__restrict__ d) {
+__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_fft_rx_inv(FftX f, const Cd *__restrict__ Wg, const typename V2<R>::type *__restrict__ spec, R *__restrict__ d) {
     extern __shared__ Cd lds[];
     const int nc = f.nr / 2, nx = f.n, h = nx / 2;
     const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
@@ -335,8 +337,8 @@ __global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(
 // FILTER: forward transform, multiply by scale p2max / p^2(k) (0 at p^2 = 0),
 // inverse transform.
 template <typename R, bool FILTER>
-__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4))) k_fft_axis(FftAxis f, const Cd *__restrict__ Wg,
-                                                        typename V2<R>::type *__restrict__ spec, int sign) {
+__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_fft_axis(FftAxis f, const Cd *__restrict__ Wg, typename V2<R>::type *__restrict__ spec, int sign) {
     extern __shared__ Cd lds[];
     const int n = f.n, np = f.np;
     const Tile t = tile_setup(lds, Wg, n, np, f.dnp);
