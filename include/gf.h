@@ -240,9 +240,9 @@ int gf_gauge_transform(gf_ctx *ctx, void *U, const void *s);
  * p^2_max / p^2 with p^2 = sum 4 sin^2(pi k / L) over the transformed axes
  * (zero mode dropped), transformed back, and g(x) = reunit(1 + (alpha/2) X)
  * (first-order exponential, Gram-Schmidt) is applied to every link. The
- * transforms are the library's own (one pass per axis, in LDS); every
- * lattice extent must be at most 1024 (GF_EUNSUPPORTED otherwise, before any
- * device work). The first call allocates about 1.5x a field of scratch (kept
+ * transforms are the library's own (one pass per axis, in LDS); nx must be
+ * at most 384 and ny, nz, nt at most 1024 (GF_EUNSUPPORTED otherwise, before
+ * any device work). The first call allocates about 1.5x a field of scratch (kept
  * by the context). Asynchronous. alpha must be > 0 (0.08 in the paper). */
 int gf_sd_step(gf_ctx *ctx, void *U, double alpha);
 

@@ -62,10 +62,9 @@ struct gf_ctx {
     void *d_gfield = nullptr;
     double *d_fpart = nullptr;
     double *d_fout = nullptr;
-    // Fourier-accelerated steepest descent: su(3) components of Delta in
-    // lexicographic order, their half spectrum, and the tables of roots of
-    // unity for the x, y, z and t lengths (FFT_MAX_N complex doubles each)
-    void *d_sd = nullptr;
+    // Fourier-accelerated steepest descent: the half spectrum of the su(3)
+    // components of Delta, and the tables of roots of unity for the x, y, z
+    // and t lengths (FFT_MAX_N complex doubles each)
     void *d_spec = nullptr;
     void *d_roots = nullptr;
 };
@@ -415,7 +414,6 @@ int gf_destroy(gf_ctx *ctx) {
     (void)hipFree(ctx->d_active);
     (void)hipFree(ctx->d_ones);
     (void)hipFree(ctx->d_iters);
-    (void)hipFree(ctx->d_sd);
     (void)hipFree(ctx->d_spec);
     (void)hipFree(ctx->d_roots);
     (void)hipFree(ctx->d_gfield);
@@ -843,21 +841,18 @@ int gf_gauge_transform(gf_ctx *ctx, void *U, const void *s) {
 
 namespace {
 
-// Buffers of one step: the eight real components d[t][a][z][y][x] and their
-// half spectrum spec[t][a][z][y][kx] (kx = 0..nx/2). Made once per context;
-// a call after a failed allocation retries what is missing.
+// Buffers of one step: the half spectrum spec[t][a][z][y][kx] (kx = 0..nx/2)
+// of the eight su(3) components of Delta, and the root tables. Made once per
+// context; a call after a failed allocation retries what is missing.
 int sd_prepare(gf_ctx *ctx) {
     const Geom &g = ctx->desc[0].g;
-    CHECK(ctx, g.nx <= FFT_MAX_N && g.ny <= FFT_MAX_N && g.nz <= FFT_MAX_N && g.nt <= FFT_MAX_N,
-          GF_EUNSUPPORTED, "Fourier acceleration supports lattice extents up to %d", FFT_MAX_N);
+    CHECK(ctx, g.nx <= FFT_MAX_NX && g.ny <= FFT_MAX_N && g.nz <= FFT_MAX_N && g.nt <= FFT_MAX_N,
+          GF_EUNSUPPORTED, "Fourier acceleration supports nx up to %d and ny, nz, nt up to %d", FFT_MAX_NX,
+          FFT_MAX_N);
     int rc;
     if ((rc = ensure_diff_scratch(ctx))) return rc;
     const size_t rs = ctx->prec == GF_F64 ? 8 : 4;
     const long long S = (long long)g.nz * g.ny * (g.nx / 2 + 1);
-    if (!ctx->d_sd && hipMalloc(&ctx->d_sd, 8 * (size_t)g.V * rs) != hipSuccess) {
-        ctx->d_sd = nullptr;
-        return fail(ctx, GF_ENOMEM, "cannot allocate the Fourier acceleration buffers");
-    }
     if (!ctx->d_spec && hipMalloc(&ctx->d_spec, 8 * (size_t)g.nt * S * 2 * rs) != hipSuccess) {
         ctx->d_spec = nullptr;
         return fail(ctx, GF_ENOMEM, "cannot allocate the Fourier acceleration buffers");
@@ -885,13 +880,14 @@ const void *sd_roots(const gf_ctx *ctx, int axis) {
 
 // One step of Alg. 2: Delta -> F (x, y, z and, for Landau, t) -> times
 // (alpha/2) p2max / p^2 / N -> F^-1 -> g = reunit(1 + X) -> U <- g U g^dagger.
-// The filter sits in the last forward pass (t for Landau, z for Coulomb),
-// between its forward and inverse transform.
+// Delta is formed in the forward x pass and g in the inverse one; the filter
+// sits in the last forward pass (t for Landau, z for Coulomb), between its
+// forward and inverse transform.
 int sd_step_impl(gf_ctx *ctx, void *U, double alpha) {
     const Geom &g = ctx->desc[0].g;
     const int gauge = ctx->desc[0].gauge;
     const bool landau = gauge == GF_LANDAU;
-    const FftX fx = make_fft_x(g);
+    const FftSite fx = make_fft_site(g);
     const FftAxis fy = make_fft_axis(g, 1, !landau);
     const FftAxis fz = make_fft_axis(g, 2, !landau);
     FftAxis flt = landau ? make_fft_axis(g, 3, false) : fz;
@@ -899,16 +895,14 @@ int sd_step_impl(gf_ctx *ctx, void *U, double alpha) {
     flt.scale = 0.5 * alpha / nfft;
     flt.p2max = landau ? 16.0 : 12.0;
     hipStream_t st = ctx->stream;
-    HIPTRY(ctx, launch_sd_delta(ctx->prec, ctx->nelem, gauge, g, U, ctx->d_sd, st));
     const void *wx = sd_roots(ctx, 0), *wy = sd_roots(ctx, 1), *wz = sd_roots(ctx, 2), *wt = sd_roots(ctx, 3);
-    HIPTRY(ctx, launch_fft_x(ctx->prec, fx, wx, ctx->d_sd, ctx->d_spec, 0, st));
+    HIPTRY(ctx, launch_sd_delta_fx(ctx->prec, ctx->nelem, gauge, g, fx, wx, U, ctx->d_spec, st));
     HIPTRY(ctx, launch_fft_axis(ctx->prec, fy, wy, ctx->d_spec, -1, 0, st));
     if (landau) HIPTRY(ctx, launch_fft_axis(ctx->prec, fz, wz, ctx->d_spec, -1, 0, st));
     HIPTRY(ctx, launch_fft_axis(ctx->prec, flt, landau ? wt : wz, ctx->d_spec, -1, 1, st));
     if (landau) HIPTRY(ctx, launch_fft_axis(ctx->prec, fz, wz, ctx->d_spec, 1, 0, st));
     HIPTRY(ctx, launch_fft_axis(ctx->prec, fy, wy, ctx->d_spec, 1, 0, st));
-    HIPTRY(ctx, launch_fft_x(ctx->prec, fx, wx, ctx->d_sd, ctx->d_spec, 1, st));
-    HIPTRY(ctx, launch_sd_gfield(ctx->prec, g, ctx->d_sd, ctx->d_gfield, st));
+    HIPTRY(ctx, launch_sd_fx_gfield(ctx->prec, g, fx, wx, ctx->d_spec, ctx->d_gfield, st));
     HIPTRY(ctx, launch_gauge_transform(ctx->prec, ctx->nelem, g, U, ctx->d_gfield, st));
     return GF_OK;
 }

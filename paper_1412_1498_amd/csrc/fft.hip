@@ -1,13 +1,18 @@
-// fft.hip -- the lattice Fourier transforms of steepest descent with Fourier
-// acceleration (Alg. 2, eqs. 8-9) on gfx950.
+// fft.hip -- steepest descent with Fourier acceleration (Alg. 2, eqs. 7-9) on
+// gfx950: Delta of eq. (3) as its eight real su(3) components, their lattice
+// Fourier transform, the p2_max / p^2(k) filter, the inverse transform, and
+// the step's gauge transformation g = reunit(1 + X) as a g field for
+// k_gauge_transform.
 //
-// The eight real su(3) components of Delta are held as d[t][a][z][y][x]; their
-// spectrum as spec[t][a][z][y][kx] with kx = 0..nx/2 (the real transform along
-// x keeps half the spectrum, the other half being its complex conjugate). One
-// pass per axis: x (real <-> half complex), then y, z and t (complex, in place);
-// the multiplication by p2_max / p^2(k) is fused into the last forward pass,
-// between its forward and inverse transform, so that pass writes back the
-// filtered field already transformed back along its own axis.
+// The components' spectrum is held as spec[t][a][z][y][kx] with kx = 0..nx/2
+// (the real transform along x keeps half the spectrum, the other half being
+// its complex conjugate). One pass per axis: x (real <-> half complex), with
+// Delta computed in the forward x pass and g formed in the inverse one, so
+// the components never go to memory in lattice space; then y, z and t
+// (complex, in place). The multiplication by p2_max / p^2(k) is fused into
+// the last forward pass, between its forward and inverse transform, so that
+// pass writes back the filtered field already transformed back along its own
+// axis.
 //
 // A workgroup loads a tile of pencils (for y, z, t: consecutive kx of one row,
 // so every global access is a contiguous run) into LDS and transforms them by
@@ -129,10 +134,8 @@ __device__ __forceinline__ void bfly5(Cd *v) {
 constexpr int pass_b(int R) { return (FFT_TILE_POINTS / R + FFT_BLOCK - 1) / FFT_BLOCK; }
 constexpr int PASS_OUT = (FFT_TILE_POINTS + FFT_BLOCK - 1) / FFT_BLOCK;
 // Global loads per thread when a tile is filled (all issued before the first
-// use, so a workgroup waits for one memory latency, not one per element):
-// complex points of an axis tile; real elements of an x tile (2 per point).
+// use, so a workgroup waits for one memory latency, not one per element).
 constexpr int LOAD_C = (FFT_TILE_POINTS + FFT_BLOCK - 1) / FFT_BLOCK;
-constexpr int LOAD_R = (2 * FFT_TILE_POINTS + FFT_BLOCK - 1) / FFT_BLOCK;
 
 // One radix-R pass of the Stockham autosort algorithm over np pencils (element
 // j of pencil q at [j * ld + q]), in place: Ns = product of the earlier
@@ -237,75 +240,177 @@ __device__ __forceinline__ double lattice_p2(int k, int L) {
 // pass's butterflies fit in that without spilling, and a CU then holds four
 // workgroups to overlap one tile's memory phase with another's passes.
 
-// Forward real transform along x: rows of nx reals -> nkx complex. Two real
-// rows a, b go through one complex transform of z = a + i b:
-// A[k] = (Z[k] + conj Z[-k]) / 2, B[k] = (Z[k] - conj Z[-k]) / 2i.
-template <typename R>
-__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
-k_fft_rx_fwd(FftX f, const Cd *__restrict__ Wg, const R *__restrict__ d, typename V2<R>::type *__restrict__ spec) {
-    extern __shared__ Cd lds[];
-    const int nc = f.nr / 2, nx = f.n;  // complex rows per workgroup
-    const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
-    const long long row0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.nr;
-    {
-        const long long lim = (f.rows - row0 < f.nr ? f.rows - row0 : f.nr) * nx;  // elements of this tile
-        R v[LOAD_R];
+namespace {
+
+// Delta(x) of eq. (3) at site (p, h) as its eight real su(3) components
+// o_a = Tr[lambda_a Delta] / (2i): M = sum_mu [U_mu(x - mu) - U_mu(x)] in
+// double, A = M - M^dagger, whose traceless part is Delta (the trace part
+// drops out of these traces, so only Im of the diagonal and the off-diagonal
+// entries of A enter).
+template <typename R, int NE>
+__device__ __forceinline__ void delta_components(const Geom &g, int nd, const gchar *U, int p, int h, double o[8]) {
+    const SiteNbr nb = site_neighbours(g, p, h);
+    double mr[9], mi[9];
 #pragma unroll
-        for (int i = 0; i < LOAD_R; i++) {
-            const int idx = threadIdx.x + i * FFT_BLOCK;
-            v[i] = idx < lim ? d[row0 * nx + idx] : (R)0;
-        }
+    for (int e = 0; e < 9; e++) { mr[e] = 0.0; mi[e] = 0.0; }
+    for (int mu = 0; mu < nd; mu++) {
+        Mat<R> f, b;
+        load_link<R, NE, false>(f, U, link_off(g, mu, p, h));
+        load_link<R, NE, false>(b, U, link_off(g, mu, 1 - p, pick4(nb.hb, mu)));
 #pragma unroll
-        for (int i = 0; i < LOAD_R; i++) {
-            const int idx = threadIdx.x + i * FFT_BLOCK;
-            if (idx < f.nr * nx) {
-                const int r = (int)fdiv((unsigned)idx, f.dn), j = idx - r * nx;
-                Cd &z = t.a[j * t.ld + (r >> 1)];
-                if (r & 1) z.y = (double)v[i]; else z.x = (double)v[i];
-            }
+        for (int e = 0; e < 9; e++) {
+            mr[e] += (double)b.re[e] - (double)f.re[e];
+            mi[e] += (double)b.im[e] - (double)f.im[e];
         }
     }
-    lds_dft<-1>(t, f.pl, nx, nc);
-    const Cd *Z = t.a;
-    for (int idx = threadIdx.x; idx < f.nr * f.nkx; idx += blockDim.x) {
-        const int r = (int)fdiv((unsigned)idx, f.dnkx), k = idx - r * f.nkx;
-        if (row0 + r < f.rows) {
-            const Cd zk = Z[k * t.ld + (r >> 1)], zm = Z[((nx - k) % nx) * t.ld + (r >> 1)];
-            typename V2<R>::type v;
-            if (r & 1) {  // (zk - conj zm) / 2i
-                v.x = (R)(0.5 * (zk.y + zm.y));
-                v.y = (R)(-0.5 * (zk.x - zm.x));
-            } else {      // (zk + conj zm) / 2
-                v.x = (R)(0.5 * (zk.x + zm.x));
-                v.y = (R)(0.5 * (zk.y - zm.y));
-            }
-            spec[(row0 + r) * f.nkx + k] = v;
+    double ar[9], ai[9];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            ar[3 * r + c] = mr[3 * r + c] - mr[3 * c + r];
+            ai[3 * r + c] = mi[3 * r + c] + mi[3 * c + r];
         }
+    const double r3 = 0.57735026918962576451;  // 1/sqrt(3)
+    o[0] = 0.5 * (ai[3] + ai[1]);
+    o[1] = 0.5 * (ar[1] - ar[3]);
+    o[2] = 0.5 * (ai[0] - ai[4]);
+    o[3] = 0.5 * (ai[6] + ai[2]);
+    o[4] = 0.5 * (ar[2] - ar[6]);
+    o[5] = 0.5 * (ai[7] + ai[5]);
+    o[6] = 0.5 * (ar[5] - ar[7]);
+    o[7] = 0.5 * r3 * (ai[0] + ai[4] - 2.0 * ai[8]);
+}
+
+// g = reunit(1 + i H), H = sum_a s_a lambda_a (the first-order exponential
+// of the step, Gram-Schmidt), in double.
+__device__ __forceinline__ void step_matrix(const double s[8], Mat<double> &m) {
+    const double r3 = 0.57735026918962576451;
+    double hr[9], hi[9];
+    hr[0] = s[2] + r3 * s[7];  hi[0] = 0.0;
+    hr[4] = -s[2] + r3 * s[7]; hi[4] = 0.0;
+    hr[8] = -2.0 * r3 * s[7];  hi[8] = 0.0;
+    hr[1] = s[0]; hi[1] = -s[1];
+    hr[3] = s[0]; hi[3] = s[1];
+    hr[2] = s[3]; hi[2] = -s[4];
+    hr[6] = s[3]; hi[6] = s[4];
+    hr[5] = s[5]; hi[5] = -s[6];
+    hr[7] = s[5]; hi[7] = s[6];
+#pragma unroll
+    for (int e = 0; e < 9; e++) {
+        m.re[e] = (e % 4 == 0 ? 1.0 : 0.0) - hi[e];
+        m.im[e] = hr[e];
+    }
+    reunitarise(m);
+}
+
+// (t, z, y) of the site rows of a tile, and z ny + y (row index within a
+// time slice), kept in LDS so each is divided out once.
+struct RowInfo {
+    int t, z, y, zy;
+};
+
+__device__ __forceinline__ void row_info(RowInfo *ri, const Geom &g, long long sr0, int ys, long long srows) {
+    for (int yl = threadIdx.x; yl < ys; yl += blockDim.x) {
+        const long long sr = sr0 + yl;
+        RowInfo r = {0, 0, 0, -1};
+        if (sr < srows) {
+            const int q = (int)(sr / g.ny);
+            r.y = (int)(sr - (long long)q * g.ny);
+            r.t = q / g.nz;
+            r.z = q - r.t * g.nz;
+            r.zy = r.z * g.ny + r.y;
+        }
+        ri[yl] = r;
     }
 }
 
-// Inverse real transform along x: nkx complex per row (the rest by conjugate
-// symmetry; the imaginary parts at kx = 0 and nx/2 are dropped, as for any
-// real inverse transform) -> nx reals, unnormalised. Rows a, b travel as
-// Z = A + i B, whose inverse is a + i b: frequency k of the pair gives
-// Z[k] = A + i B and Z[nx - k] = conj A + i conj B.
+// spec[t][a][z][y][kx] index of component a, kx of a site row
+__device__ __forceinline__ long long spec_index(const Geom &g, int nkx, const RowInfo &r, int a, int k) {
+    return (((long long)r.t * 8 + a) * g.nz * g.ny + r.zy) * nkx + k;
+}
+
+}  // namespace
+
+// Delta and its forward real transform along x, for ys site rows (lines
+// along x at fixed y, z, t; consecutive in (t, z, y)). The eight components of
+// a site row travel as four complex rows, components 2c + i (2c + 1) in
+// pencil 4 yl + c; after the transform A[k] = (Z[k] + conj Z[-k]) / 2 and
+// B[k] = (Z[k] - conj Z[-k]) / 2i are the two components' spectra. A site
+// row holds both parities, so a site's x-backward link is the other
+// parity's forward link of the same tile and its y-backward link that of the
+// previous row.
+template <typename R, int NE>
+__global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
+k_sd_delta_fx(Geom g, int nd, const typename V2<R>::type *__restrict__ Uv, FftSite f, const Cd *__restrict__ Wg,
+              typename V2<R>::type *__restrict__ spec) {
+    extern __shared__ Cd lds[];
+    const int nx = g.nx, nc = 4 * f.ys;
+    const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
+    RowInfo *ri = (RowInfo *)(t.Wl + nx);
+    const long long sr0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.ys;
+    row_info(ri, g, sr0, f.ys, f.srows);
+    __syncthreads();
+    const gchar *U = as_global((const void *)Uv);
+    for (int idx = threadIdx.x; idx < f.ys * nx; idx += blockDim.x) {
+        const int yl = (int)fdiv((unsigned)idx, f.dn), x = idx - yl * nx;
+        const RowInfo r = ri[yl];
+        double o[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (r.zy >= 0) {
+            const int lx = x + nx * (int)(sr0 + yl);  // x + nx (y + ny (z + nz t))
+            delta_components<R, NE>(g, nd, U, (x + r.y + r.z + r.t) & 1, lx >> 1, o);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; c++) t.a[x * t.ld + yl * 4 + c] = Cd{o[2 * c], o[2 * c + 1]};
+    }
+    lds_dft<-1>(t, f.pl, nx, nc);
+    for (int idx = threadIdx.x; idx < 8 * f.ys * f.nkx; idx += blockDim.x) {
+        const int row = (int)fdiv((unsigned)idx, f.dnkx), k = idx - row * f.nkx;
+        const int yl = row >> 3, a = row & 7;
+        const RowInfo r = ri[yl];
+        if (r.zy < 0) continue;
+        const int cr = yl * 4 + (a >> 1);
+        const Cd zk = t.a[k * t.ld + cr], zm = t.a[((nx - k) % nx) * t.ld + cr];
+        typename V2<R>::type v;
+        if (a & 1) {  // (zk - conj zm) / 2i
+            v.x = (R)(0.5 * (zk.y + zm.y));
+            v.y = (R)(-0.5 * (zk.x - zm.x));
+        } else {      // (zk + conj zm) / 2
+            v.x = (R)(0.5 * (zk.x + zm.x));
+            v.y = (R)(0.5 * (zk.y - zm.y));
+        }
+        spec[spec_index(g, f.nkx, r, a, k)] = v;
+    }
+}
+
+// Inverse real transform along x of ys site rows' eight component spectra
+// (the rest of each by conjugate symmetry; the imaginary parts at kx = 0 and
+// nx/2 are dropped, as for any real inverse transform), components 2c and
+// 2c + 1 travelling as Z = A + i B; then every site's step matrix
+// g = reunit(1 + i sum_a s_a lambda_a), written as the g field [e][p][h].
 template <typename R>
 __global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
-k_fft_rx_inv(FftX f, const Cd *__restrict__ Wg, const typename V2<R>::type *__restrict__ spec, R *__restrict__ d) {
+k_sd_fx_gfield(Geom g, FftSite f, const Cd *__restrict__ Wg, const typename V2<R>::type *__restrict__ spec,
+               typename V2<R>::type *__restrict__ gf) {
     extern __shared__ Cd lds[];
-    const int nc = f.nr / 2, nx = f.n, h = nx / 2;
+    const int nx = g.nx, nc = 4 * f.ys, h = nx / 2;
     const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
-    const long long row0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.nr;
+    RowInfo *ri = (RowInfo *)(t.Wl + nx);
+    const long long sr0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.ys;
+    row_info(ri, g, sr0, f.ys, f.srows);
+    __syncthreads();
     typename V2<R>::type va[LOAD_C], vb[LOAD_C];
 #pragma unroll
-    for (int i = 0; i < LOAD_C; i++) {
+    for (int i = 0; i < LOAD_C; i++) {  // nc nkx <= FFT_TILE_POINTS (pencil, frequency) pairs
         const int idx = threadIdx.x + i * FFT_BLOCK;
         va[i].x = va[i].y = vb[i].x = vb[i].y = (R)0;
         if (idx < nc * f.nkx) {
-            const int c = (int)fdiv((unsigned)idx, f.dnkx), k = idx - c * f.nkx;
-            if (row0 + 2 * c < f.rows) {
-                va[i] = spec[(row0 + 2 * c) * f.nkx + k];
-                vb[i] = spec[(row0 + 2 * c + 1) * f.nkx + k];
+            const int cr = (int)fdiv((unsigned)idx, f.dnkx), k = idx - cr * f.nkx;
+            const RowInfo r = ri[cr >> 2];
+            if (r.zy >= 0) {
+                const int a = 2 * (cr & 3);
+                va[i] = spec[spec_index(g, f.nkx, r, a, k)];
+                vb[i] = spec[spec_index(g, f.nkx, r, a + 1, k)];
             }
         }
     }
@@ -313,21 +418,37 @@ k_fft_rx_inv(FftX f, const Cd *__restrict__ Wg, const typename V2<R>::type *__re
     for (int i = 0; i < LOAD_C; i++) {
         const int idx = threadIdx.x + i * FFT_BLOCK;
         if (idx >= nc * f.nkx) continue;
-        const int c = (int)fdiv((unsigned)idx, f.dnkx), k = idx - c * f.nkx;
+        const int cr = (int)fdiv((unsigned)idx, f.dnkx), k = idx - cr * f.nkx;
         const Cd A = Cd{(double)va[i].x, (double)va[i].y}, B = Cd{(double)vb[i].x, (double)vb[i].y};
         if (k == 0 || k == h) {
-            t.a[k * t.ld + c] = Cd{A.x, B.x};
+            t.a[k * t.ld + cr] = Cd{A.x, B.x};
         } else {
-            t.a[k * t.ld + c] = Cd{A.x - B.y, A.y + B.x};
-            t.a[(nx - k) * t.ld + c] = Cd{A.x + B.y, B.x - A.y};
+            t.a[k * t.ld + cr] = Cd{A.x - B.y, A.y + B.x};
+            t.a[(nx - k) * t.ld + cr] = Cd{A.x + B.y, B.x - A.y};
         }
     }
     lds_dft<1>(t, f.pl, nx, nc);
-    for (int idx = threadIdx.x; idx < f.nr * nx; idx += blockDim.x) {
-        const int r = (int)fdiv((unsigned)idx, f.dn), j = idx - r * nx;
-        if (row0 + r < f.rows) {
-            const Cd v = t.a[j * t.ld + (r >> 1)];
-            d[(row0 + r) * nx + j] = (R)((r & 1) ? v.y : v.x);
+    for (int idx = threadIdx.x; idx < f.ys * nx; idx += blockDim.x) {
+        const int yl = (int)fdiv((unsigned)idx, f.dn), x = idx - yl * nx;
+        const RowInfo r = ri[yl];
+        if (r.zy < 0) continue;
+        double sv[8];
+#pragma unroll
+        for (int c = 0; c < 4; c++) {
+            const Cd z = t.a[x * t.ld + yl * 4 + c];
+            sv[2 * c] = z.x;
+            sv[2 * c + 1] = z.y;
+        }
+        Mat<double> m;
+        step_matrix(sv, m);
+        const int lx = x + nx * (int)(sr0 + yl);
+        const int n = ((x + r.y + r.z + r.t) & 1) * g.Vh + (lx >> 1);
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            typename V2<R>::type v;
+            v.x = (R)m.re[e];
+            v.y = (R)m.im[e];
+            gf[(long long)e * g.V + n] = v;
         }
     }
 }
@@ -424,17 +545,16 @@ static FftPlan plan_length(int n) {
     return p;
 }
 
-FftX make_fft_x(const Geom &g) {
-    FftX f;
+FftSite make_fft_site(const Geom &g) {
+    FftSite f;
     f.n = g.nx;
     f.nkx = g.nx / 2 + 1;
     f.pl = plan_length(f.n);
-    const int nc = FFT_TILE_POINTS / g.nx > 0 ? FFT_TILE_POINTS / g.nx : 1;  // complex rows
-    f.nr = 2 * nc;
-    f.rows = (long long)g.nt * 8 * g.nz * g.ny;
+    f.ys = FFT_TILE_POINTS / (4 * g.nx);  // site rows per workgroup (>= 1: nx <= FFT_MAX_NX)
+    f.srows = (long long)g.nt * g.nz * g.ny;
     f.dn = make_fastdiv((unsigned)f.n);
     f.dnkx = make_fastdiv((unsigned)f.nkx);
-    f.dnc = make_fastdiv((unsigned)nc);
+    f.dnc = make_fastdiv((unsigned)(4 * f.ys));
     return f;
 }
 
@@ -477,25 +597,36 @@ hipError_t launch_fft_roots(void *W, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_fft_x(int prec, const FftX &f, const void *W, void *d, void *spec, int inverse, hipStream_t st) {
-    const dim3 grid((unsigned)((f.rows + f.nr - 1) / f.nr));
-    const size_t sh = lds_bytes(f.n, f.nr / 2 + 1);
+static size_t site_lds_bytes(const FftSite &f) {
+    return lds_bytes(f.n, 4 * f.ys + 1) + (size_t)f.ys * sizeof(RowInfo);
+}
+
+hipError_t launch_sd_delta_fx(int prec, int nelem, int gauge, const Geom &g, const FftSite &f, const void *W,
+                              const void *U, void *spec, hipStream_t st) {
+    const dim3 grid((unsigned)((f.srows + f.ys - 1) / f.ys));
+    const size_t sh = site_lds_bytes(f);
+    const int nd = gauge == 0 ? 4 : 3;
     const Cd *w = (const Cd *)W;
-    if (prec == 0) {
-        if (inverse)
-            hipLaunchKernelGGL(k_fft_rx_inv<double>, grid, dim3(FFT_BLOCK), sh, st, f, w,
-                               (const V2<double>::type *)spec, (double *)d);
-        else
-            hipLaunchKernelGGL(k_fft_rx_fwd<double>, grid, dim3(FFT_BLOCK), sh, st, f, w, (const double *)d,
-                               (V2<double>::type *)spec);
-    } else {
-        if (inverse)
-            hipLaunchKernelGGL(k_fft_rx_inv<float>, grid, dim3(FFT_BLOCK), sh, st, f, w,
-                               (const V2<float>::type *)spec, (float *)d);
-        else
-            hipLaunchKernelGGL(k_fft_rx_fwd<float>, grid, dim3(FFT_BLOCK), sh, st, f, w, (const float *)d,
-                               (V2<float>::type *)spec);
-    }
+#define GF_L(R, NE)                                                                                   \
+    hipLaunchKernelGGL((k_sd_delta_fx<R, NE>), grid, dim3(FFT_BLOCK), sh, st, g, nd,                 \
+                       (const V2<R>::type *)U, f, w, (V2<R>::type *)spec)
+    if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
+    else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
+#undef GF_L
+    return hipGetLastError();
+}
+
+hipError_t launch_sd_fx_gfield(int prec, const Geom &g, const FftSite &f, const void *W, const void *spec,
+                               void *gfield, hipStream_t st) {
+    const dim3 grid((unsigned)((f.srows + f.ys - 1) / f.ys));
+    const size_t sh = site_lds_bytes(f);
+    const Cd *w = (const Cd *)W;
+    if (prec == 0)
+        hipLaunchKernelGGL(k_sd_fx_gfield<double>, grid, dim3(FFT_BLOCK), sh, st, g, f, w,
+                           (const V2<double>::type *)spec, (V2<double>::type *)gfield);
+    else
+        hipLaunchKernelGGL(k_sd_fx_gfield<float>, grid, dim3(FFT_BLOCK), sh, st, g, f, w,
+                           (const V2<float>::type *)spec, (V2<float>::type *)gfield);
     return hipGetLastError();
 }
 

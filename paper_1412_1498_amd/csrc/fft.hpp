@@ -6,14 +6,17 @@
 
 namespace gf {
 
-// Lattice Fourier transforms of Alg. 2 (fft.hip). Real field d[t][a][z][y][x],
-// spectrum spec[t][a][z][y][kx], kx = 0..nx/2. A workgroup transforms a tile
+// Lattice Fourier transforms of Alg. 2 (fft.hip). Spectrum of the eight
+// components spec[t][a][z][y][kx], kx = 0..nx/2. A workgroup transforms a tile
 // of at most FFT_TILE_POINTS complex points in LDS (in place, in double, with
 // the roots: <= 40 KB), so an axis may be at most FFT_MAX_N long (whose
 // radices take at most FFT_MAX_PASSES passes).
 constexpr int FFT_BLOCK = 256;
 constexpr int FFT_TILE_POINTS = 1536;
 constexpr int FFT_MAX_N = 1024;
+// Along x a tile holds the eight components of whole site rows (four complex
+// pencils per row), so nx is at most FFT_TILE_POINTS / 4.
+constexpr int FFT_MAX_NX = FFT_TILE_POINTS / 4;
 
 // Division by a small divisor d as a multiply-high: floor(n / d) =
 // (n * ceil(2^32 / d)) >> 32 exactly for n, d < 2^16 (d = 1 kept apart).
@@ -37,13 +40,13 @@ struct FftPlan {     // radices of the Stockham passes, in order
     FastDiv ns[FFT_MAX_PASSES];  // division by Ns = product of the earlier radices
 };
 
-struct FftX {        // real <-> half-complex along x
-    int n;           // nx
+struct FftSite {      // Delta and the real <-> half-complex transform along x, by site rows
+    int n;            // nx
     FftPlan pl;
-    int nkx;         // nx / 2 + 1
-    int nr;          // real rows per workgroup (even: rows travel in pairs)
-    long long rows;  // nt * 8 * nz * ny
-    FastDiv dn, dnkx, dnc;  // division by nx, nkx and nr / 2
+    int nkx;          // nx / 2 + 1
+    int ys;           // site rows (lines along x) per workgroup: 4 ys complex pencils
+    long long srows;  // nt * nz * ny
+    FastDiv dn, dnkx, dnc;  // division by nx, nkx and 4 ys
 };
 
 struct FftAxis {     // complex, in place, along y, z or t
@@ -58,11 +61,16 @@ struct FftAxis {     // complex, in place, along y, z or t
     FastDiv dnp;          // division by np
 };
 
-FftX make_fft_x(const Geom &g);
+FftSite make_fft_site(const Geom &g);
 FftAxis make_fft_axis(const Geom &g, int axis, bool coulomb);  // axis 1 = y, 2 = z, 3 = t
 // W: a table of exp(2 pi i m / n), m < n, for the transform's length (launch_fft_roots fills it)
 hipError_t launch_fft_roots(void *W, int n, hipStream_t st);
-hipError_t launch_fft_x(int prec, const FftX &f, const void *W, void *d, void *spec, int inverse, hipStream_t st);
+// Delta (eq. 3) of every site -> its components' x-transformed half spectrum
+hipError_t launch_sd_delta_fx(int prec, int nelem, int gauge, const Geom &g, const FftSite &f, const void *W,
+                              const void *U, void *spec, hipStream_t st);
+// half spectrum -> inverse x transform -> g = reunit(1 + X) as the g field [e][p][h]
+hipError_t launch_sd_fx_gfield(int prec, const Geom &g, const FftSite &f, const void *W, const void *spec,
+                               void *gfield, hipStream_t st);
 hipError_t launch_fft_axis(int prec, const FftAxis &f, const void *W, void *spec, int sign, int filter,
                            hipStream_t st);
 

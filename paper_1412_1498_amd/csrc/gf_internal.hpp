@@ -142,8 +142,5 @@ hipError_t launch_functional_grad(int prec, int nelem, int gauge, const Geom &g,
 hipError_t launch_gauge_transform(int prec, int nelem, const Geom &g, void *U, const void *gfield,
                                   hipStream_t st);
 hipError_t launch_sum_partials(const double *d_partials, int n, double *d_out, hipStream_t st);
-hipError_t launch_sd_delta(int prec, int nelem, int gauge, const Geom &g, const void *U, void *d,
-                           hipStream_t st);
-hipError_t launch_sd_gfield(int prec, const Geom &g, const void *d, void *gfield, hipStream_t st);
 
 }  // namespace gf

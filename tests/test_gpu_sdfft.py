@@ -60,11 +60,12 @@ def filter_gain(dims, gauge):
 
 
 @pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
-@pytest.mark.parametrize("dims", [(1024, 2, 2, 2), (2, 1018, 2, 2), (2, 2, 1022, 2), (2, 2, 2, 1000)])
+@pytest.mark.parametrize("dims", [(384, 2, 2, 2), (2, 1024, 2, 2), (2, 1018, 2, 2), (2, 2, 1022, 2), (2, 2, 2, 1000)])
 def test_sd_step_long_axes(gf, field_cache, gauge, dims):
-    """One long axis, FP64: tiles at their size limit (1024 = 4^5, one pencil
-    per workgroup), the direct-sum pass of large prime factors (1018 = 2 509,
-    1022 = 2 7 73) and radix 5 (1000 = 4 2 5 5 5)."""
+    """One long axis, FP64: tiles at their size limit (x: 384, one site row
+    per workgroup; y: 1024 = 4^5, one pencil per workgroup), the direct-sum
+    pass of large prime factors (1018 = 2 509, 1022 = 2 7 73) and radix 5
+    (1000 = 4 2 5 5 5)."""
     U = field_cache(dims, 0.4, 72)
     ctx, Ug = setup(gf, dims, gauge, 0, U)
     ctx.sd_step(Ug, 0.08)
@@ -123,10 +124,12 @@ def test_sd_rejects_bad_alpha(gf, field_cache):
         assert e.value.code == gf.EINVAL
 
 
-def test_sd_rejects_extents_beyond_the_transform_tile(gf):
-    """An extent above 1024 does not fit one transform tile: refused before
-    any kernel runs."""
-    ctx = gf.Context((1026, 2, 2, 2), gauge=LANDAU, prec=1)
+@pytest.mark.parametrize("dims", [(386, 2, 2, 2), (2, 1026, 2, 2), (2, 2, 2, 1026)])
+def test_sd_rejects_extents_beyond_the_transform_tile(gf, dims):
+    """nx above 384 (a tile holds four complex pencils of each site row) or
+    another extent above 1024 does not fit one transform tile: refused
+    before any kernel runs."""
+    ctx = gf.Context(dims, gauge=LANDAU, prec=1)
     U = ctx.empty_field()
     with pytest.raises(gf.GFError) as e:
         ctx.sd_step(U, 0.08)
