@@ -9,78 +9,11 @@
 //     dF/ds_a(x) = (1/(d N_c V)) Re Tr[X_a Psi],  Psi = sum_k ad_S^k(K e^S)/(k+1)!,
 // one series on a 3x3 matrix per site followed by eight traces. At s = 0 it
 // reduces to Re Tr[X_a K(x)] / (d N_c V).
+#include "dmat.hpp"
 #include "su3_device.hpp"
 #include "tile_order.hpp"
 
 namespace gf {
-
-struct DMat {
-    double re[9], im[9];
-};
-
-// 3x3 complex products in double, each element an FMA chain (4 per complex
-// multiply-add).
-__device__ __forceinline__ void dm_mul(const DMat &a, const DMat &b, DMat &c) {
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            double r = a.re[3 * i] * b.re[j], m = a.re[3 * i] * b.im[j];
-            r = fma(-a.im[3 * i], b.im[j], r);
-            m = fma(a.im[3 * i], b.re[j], m);
-#pragma unroll
-            for (int k = 1; k < 3; k++) {
-                r = fma(a.re[3 * i + k], b.re[3 * k + j], r);
-                r = fma(-a.im[3 * i + k], b.im[3 * k + j], r);
-                m = fma(a.re[3 * i + k], b.im[3 * k + j], m);
-                m = fma(a.im[3 * i + k], b.re[3 * k + j], m);
-            }
-            c.re[3 * i + j] = r;
-            c.im[3 * i + j] = m;
-        }
-}
-
-// a * b^dagger
-__device__ __forceinline__ void dm_mul_nd(const DMat &a, const DMat &b, DMat &c) {
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            double r = a.re[3 * i] * b.re[3 * j], m = a.im[3 * i] * b.re[3 * j];
-            r = fma(a.im[3 * i], b.im[3 * j], r);
-            m = fma(-a.re[3 * i], b.im[3 * j], m);
-#pragma unroll
-            for (int k = 1; k < 3; k++) {
-                r = fma(a.re[3 * i + k], b.re[3 * j + k], r);
-                r = fma(a.im[3 * i + k], b.im[3 * j + k], r);
-                m = fma(a.im[3 * i + k], b.re[3 * j + k], m);
-                m = fma(-a.re[3 * i + k], b.im[3 * j + k], m);
-            }
-            c.re[3 * i + j] = r;
-            c.im[3 * i + j] = m;
-        }
-}
-
-// a^dagger * b^dagger: element (i, j) = sum_k conj(a_ki) conj(b_jk)
-__device__ __forceinline__ void dm_mul_dd(const DMat &a, const DMat &b, DMat &c) {
-#pragma unroll
-    for (int i = 0; i < 3; i++)
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            double r = a.re[i] * b.re[3 * j], m = -a.re[i] * b.im[3 * j];
-            r = fma(-a.im[i], b.im[3 * j], r);
-            m = fma(-a.im[i], b.re[3 * j], m);
-#pragma unroll
-            for (int k = 1; k < 3; k++) {
-                r = fma(a.re[3 * k + i], b.re[3 * j + k], r);
-                r = fma(-a.im[3 * k + i], b.im[3 * j + k], r);
-                m = fma(-a.re[3 * k + i], b.im[3 * j + k], m);
-                m = fma(-a.im[3 * k + i], b.re[3 * j + k], m);
-            }
-            c.re[3 * i + j] = r;
-            c.im[3 * i + j] = m;
-        }
-}
 
 // S = i sum_a s_a lambda_a / 2 (anti-hermitian, traceless).
 __device__ __forceinline__ void algebra_matrix(const double s[8], DMat &S) {
@@ -139,24 +72,6 @@ template <typename R>
 __device__ __forceinline__ void load_s(const R *__restrict__ s, int V, int n, double out[8]) {
 #pragma unroll
     for (int a = 0; a < 8; a++) out[a] = (double)s[(long long)a * V + n];
-}
-
-template <typename R>
-__device__ __forceinline__ void load_g(const typename V2<R>::type *__restrict__ gf, int V, int n, DMat &m) {
-#pragma unroll
-    for (int e = 0; e < 9; e++) {
-        typename V2<R>::type v = gf[(long long)e * V + n];
-        m.re[e] = v.x;
-        m.im[e] = v.y;
-    }
-}
-
-template <typename R, int NE, bool NT = false>
-__device__ __forceinline__ void load_u(const typename V2<R>::type *__restrict__ U, long long off, DMat &m) {
-    Mat<R> t;
-    load_link<R, NE, NT>(t, as_global((const void *)U), off);
-#pragma unroll
-    for (int e = 0; e < 9; e++) { m.re[e] = t.re[e]; m.im[e] = t.im[e]; }
 }
 
 // g field (9 complex per site, layout [e][p][h]) from s.
@@ -319,14 +234,11 @@ __global__ void __launch_bounds__(GT_TILE) k_gauge_transform(Geom g, typename V2
     DMat gx;
     load_g<R>(gf, g.V, n, gx);
     for (int mu = 0; mu < 4; mu++) {
-        DMat u, gy, t, r;
+        DMat u, gy;
         load_u<R, NE, true>(U, link_off(g, mu, p, h), u);  // each link is read and written once: stream
         load_g<R>(gf, g.V, (1 - p) * g.Vh + pick4(fw.hb, mu), gy);
-        dm_mul(gx, u, t);
-        dm_mul_nd(t, gy, r);
         Mat<R> m;
-#pragma unroll
-        for (int e = 0; e < 9; e++) { m.re[e] = (R)r.re[e]; m.im[e] = (R)r.im[e]; }
+        gauge_rotate<R>(gx, u, gy, m);
         store_link<R, NE, true>(m, as_global((void *)U), link_off(g, mu, p, h));
     }
 }

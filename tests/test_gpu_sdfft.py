@@ -101,6 +101,27 @@ def test_sd_fix_matches_oracle(gf, oracle_lib, field_cache, gauge):
     assert abs(r["F"] - ro["F"]) < 1e-12
 
 
+@pytest.mark.parametrize("storage", [0, 1, 2])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("check_every,max_iter", [(4, 7), (3, 3), (1, 2)])
+def test_sd_fix_equals_repeated_steps(gf, field_cache, storage, prec, gauge, check_every, max_iter):
+    """gf_sd_fix, with checks every check_every steps and a last period cut
+    by max_iter, returns bitwise the field, F and theta of gf_sd_step
+    repeated and a quality evaluation."""
+    dims = (6, 4, 4, 8)
+    U = field_cache(dims, 0.4, 74)
+    c1, U1 = setup(gf, dims, gauge, prec, U, storage=storage, check_every=check_every)
+    c2, U2 = setup(gf, dims, gauge, prec, U, storage=storage)
+    r = c1.sd_fix(U1, 0.08, 0.0, max_iter)
+    for _ in range(max_iter):
+        c2.sd_step(U2, 0.08)
+    F2, th2 = c2.quality(U2)
+    assert r["iters"] == max_iter and not r["converged"]
+    assert torch.equal(U1, U2)
+    assert r["F"] == F2 and r["theta"] == th2
+
+
 def test_sd_fft_fp32_reaches_1e7_and_tracks_or(gf, field_cache):
     """Alg. 2 in FP32 reaches theta < 1e-7 and lands on the same maximum as
     overrelaxation (Alg. 1) from the same start."""
