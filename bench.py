@@ -371,6 +371,8 @@ def main():
             "achieved_gbs": rf64["achieved_gbs"],
             "frac": rf64["achieved_gbs"] / PEAK_HBM_GBS,
             "avg_launch_us": rf64["avg_launch_s"] * 1e6,
+            "traffic": (measured_traffic(f"halfsweep_{'x'.join(map(str, dims))}_f64_{args.storage}real_pmc.txt", khash)
+                        if args.storage == 18 else None),
             "schedule": r64["schedule"],
         }
         out["fp32_over_fp64_throughput"] = value / out["fp64"]["value"]
