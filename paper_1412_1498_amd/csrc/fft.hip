@@ -65,8 +65,14 @@ __device__ __forceinline__ Tile tile_setup(Cd *lds, const Cd *__restrict__ Wg, i
     t.ld = ld;
     t.dnp = dnp;
     t.Wl = lds + n * ld;
+    return t;
+}
+
+// The n roots into the tile: called after the tile's own loads are issued,
+// so their latency overlaps those instead of preceding them (lds_dft begins
+// with a barrier).
+__device__ __forceinline__ void load_roots(const Tile &t, const Cd *__restrict__ Wg, int n) {
     for (int m = threadIdx.x; m < n; m += blockDim.x) t.Wl[m] = Wg[m];
-    return t;  // lds_dft begins with a barrier
 }
 
 // w or its conjugate: the table holds exp(+2 pi i m / n); SIGN = -1 forward.
@@ -347,6 +353,7 @@ k_sd_delta_fx(Geom g, int nd, const typename V2<R>::type *__restrict__ Uv, FftSi
     extern __shared__ Cd lds[];
     const int nx = g.nx, nc = 4 * f.ys;
     const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
+    load_roots(t, Wg, nx);
     RowInfo *ri = (RowInfo *)(t.Wl + nx);
     const long long sr0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.ys;
     row_info(ri, g, sr0, f.ys, f.srows);
@@ -414,6 +421,7 @@ k_sd_fx_gfield(Geom g, FftSite f, const Cd *__restrict__ Wg, const typename V2<R
             }
         }
     }
+    load_roots(t, Wg, nx);
 #pragma unroll
     for (int i = 0; i < LOAD_C; i++) {
         const int idx = threadIdx.x + i * FFT_BLOCK;
@@ -484,6 +492,7 @@ k_fft_axis(FftAxis f, const Cd *__restrict__ Wg, typename V2<R>::type *__restric
                 if (kx0 + q < f.nkx) v[i] = spec[base + j * f.s_ax + q];
             }
         }
+        load_roots(t, Wg, n);
 #pragma unroll
         for (int i = 0; i < LOAD_C; i++) {
             const int idx = threadIdx.x + i * FFT_BLOCK;
