@@ -191,6 +191,37 @@ def run_sun(args, dims, gf, synth, torch):
     return res
 
 
+def run_sd(args, dims, gf, synth, torch):
+    """Fourier-accelerated steepest descent (Alg. 2, alpha 0.08, Landau) on the
+    main lattice, FP32 and FP64 (amp 0.7, seed 0): the time of one step
+    (2 warm-up and 20 timed gf_sd_step calls) and a run to theta < 1e-7 with a
+    check every 10 steps."""
+    res = {}
+    U64 = synth.random_gauge_field(dims, args.amp, args.seed, device="cuda")
+    for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
+        log(f"Alg. 2 steps at {'x'.join(map(str, dims))}, {name}")
+        ctx = gf.Context(dims, prec=prec, params=gf.default_params(prec, check_every=10))
+        U = ctx.pack(U64 if prec == gf.F64 else U64.to(torch.complex64))
+        for _ in range(2):
+            ctx.sd_step(U, 0.08)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            ctx.sd_step(U, 0.08)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) / 20 * 1e3
+        U = ctx.pack(U64 if prec == gf.F64 else U64.to(torch.complex64), U)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.sd_fix(U, 0.08, 1e-7, 5000)
+        torch.cuda.synchronize()
+        res[name] = {"step_ms": step_ms, "seconds_to_theta_1e-7": time.perf_counter() - t0, "steps": r["iters"],
+                     "converged": r["converged"], "F": r["F"], "theta": r["theta"]}
+        del U, ctx
+        torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -212,9 +243,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation timing leg")
     ap.add_argument("--no-sun", action="store_true", help="skip the SU(2) / SU(4) leg")
-    ap.add_argument("--workload", choices=["single", "ensemble", "sun"], default="single",
+    ap.add_argument("--workload", choices=["single", "ensemble", "sun", "sd"], default="single",
                     help="ensemble: Coulomb 48^3x96 plus 64 Landau lattices of uneven volume fixed together; "
-                         "sun: only the SU(2) / SU(4) leg")
+                         "sun: only the SU(2) / SU(4) leg; sd: only steepest descent with Fourier acceleration")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch one plain 1 GiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -237,6 +268,15 @@ def main():
     if args.workload == "sun":
         print(json.dumps({"workload": "SU(2) and SU(4) overrelaxation, Landau gauge",
                           "sun": run_sun(args, dims, gf, synth, torch)}), flush=True)
+        return
+    if args.workload == "sd":
+        out = {"workload": "steepest descent with Fourier acceleration (Alg. 2), Landau gauge, alpha 0.08",
+               "sd": run_sd(args, dims, gf, synth, torch)}
+        if args.copy_probe:
+            a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+            torch.empty_like(a).copy_(a)
+            torch.cuda.synchronize()
+        print(json.dumps(out), flush=True)
         return
     V = dims[0] * dims[1] * dims[2] * dims[3]
     spp = args.sweeps_per_step
