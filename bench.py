@@ -191,6 +191,43 @@ def run_sun(args, dims, gf, synth, torch):
     return res
 
 
+def run_diff(gf, synth, torch):
+    """Differentiation line: F_U[g] and its hand-written backward at 24^4
+    (amp 0.4, s_a ~ N(0, 0.1^2)), FP32 and FP64; 20 timed calls each."""
+    ddims = (24, 24, 24, 24)
+    Vd = 24 ** 4
+    Ud = synth.random_gauge_field(ddims, 0.4, 0, device="cuda")
+    sd = synth.random_algebra_field(ddims, 0.1, 1)
+    diffres = {}
+    for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
+        ctx = gf.Context(ddims, gauge=gf.LANDAU, prec=prec)
+        U = ctx.pack(Ud.to(ctx.cdtype))
+        s = ctx.pack_alg(sd.to("cuda", dtype=ctx.rdtype))
+        grad = ctx.functional_grad(U, s)
+        ctx.functional(U, s)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(20):
+            ctx.functional(U, s)
+        tf = (time.perf_counter() - t0) / 20
+        t0 = time.perf_counter()
+        for _ in range(20):
+            ctx.functional_grad(U, s, 1.0, out=grad)
+        torch.cuda.synchronize()
+        tb = (time.perf_counter() - t0) / 20
+        t0 = time.perf_counter()
+        for _ in range(20):
+            ctx.gauge_transform(U, s)
+        torch.cuda.synchronize()
+        tg = (time.perf_counter() - t0) / 20
+        diffres[name] = dict(forward_ms=tf * 1e3, backward_ms=tb * 1e3, gauge_transform_ms=tg * 1e3,
+                             sites_per_s_backward=Vd / tb)
+        del U, s, grad, ctx
+    del Ud
+    torch.cuda.empty_cache()
+    return diffres
+
+
 def run_sd(args, dims, gf, synth, torch):
     """Fourier-accelerated steepest descent (Alg. 2, alpha 0.08, Landau) on the
     main lattice, FP32 and FP64 (amp 0.7, seed 0): the time of one step
@@ -243,9 +280,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation timing leg")
     ap.add_argument("--no-sun", action="store_true", help="skip the SU(2) / SU(4) leg")
-    ap.add_argument("--workload", choices=["single", "ensemble", "sun", "sd"], default="single",
+    ap.add_argument("--workload", choices=["single", "ensemble", "sun", "sd", "diff"], default="single",
                     help="ensemble: Coulomb 48^3x96 plus 64 Landau lattices of uneven volume fixed together; "
-                         "sun: only the SU(2) / SU(4) leg; sd: only steepest descent with Fourier acceleration")
+                         "sun: only the SU(2) / SU(4) leg; sd: only steepest descent with Fourier acceleration; "
+                         "diff: only the differentiation leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also launch one plain 1 GiB device copy (counter scale reference)")
     args = ap.parse_args()
@@ -268,6 +306,10 @@ def main():
     if args.workload == "sun":
         print(json.dumps({"workload": "SU(2) and SU(4) overrelaxation, Landau gauge",
                           "sun": run_sun(args, dims, gf, synth, torch)}), flush=True)
+        return
+    if args.workload == "diff":
+        print(json.dumps({"workload": "differentiation: F_U[g], its gradient and the gauge transformation, 24^4",
+                          "differentiation_24x4": run_diff(gf, synth, torch)}), flush=True)
         return
     if args.workload == "sd":
         out = {"workload": "steepest descent with Fourier acceleration (Alg. 2), Landau gauge, alpha 0.08",
@@ -474,34 +516,7 @@ def main():
         out["convergence"] = conv
 
     if not args.no_diff:
-        # differentiation line: F_U[g] and its hand-written backward at 24^4
-        # (amp 0.4, s_a ~ N(0, 0.1^2)), FP32 and FP64
-        ddims = (24, 24, 24, 24)
-        Vd = 24 ** 4
-        Ud = synth.random_gauge_field(ddims, 0.4, 0, device="cuda")
-        sd = synth.random_algebra_field(ddims, 0.1, 1)
-        diffres = {}
-        for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
-            ctx = gf.Context(ddims, gauge=gf.LANDAU, prec=prec)
-            U = ctx.pack(Ud.to(ctx.cdtype))
-            s = ctx.pack_alg(sd.to("cuda", dtype=ctx.rdtype))
-            grad = ctx.functional_grad(U, s)
-            ctx.functional(U, s)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(20):
-                ctx.functional(U, s)
-            tf = (time.perf_counter() - t0) / 20
-            t0 = time.perf_counter()
-            for _ in range(20):
-                ctx.functional_grad(U, s, 1.0, out=grad)
-            torch.cuda.synchronize()
-            tb = (time.perf_counter() - t0) / 20
-            diffres[name] = dict(forward_ms=tf * 1e3, backward_ms=tb * 1e3, sites_per_s_backward=Vd / tb)
-            del U, s, grad, ctx
-        out["differentiation_24x4"] = diffres
-        del Ud
-        torch.cuda.empty_cache()
+        out["differentiation_24x4"] = run_diff(gf, synth, torch)
 
     if not args.no_sun:
         out["sun"] = run_sun(args, dims, gf, synth, torch)
