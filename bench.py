@@ -191,6 +191,32 @@ def run_sun(args, dims, gf, synth, torch):
     return res
 
 
+def bw_reference(torch, nbytes, achieved_gbs):
+    """HBM reference on the same GPU: torch's device copy (read one buffer,
+    write another) and an in-place negation (read and write one buffer, the
+    half-sweep's access kind), each over nbytes per buffer; 3 warm-up and 10
+    timed launches, HIP events on torch's stream."""
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    res = {"buffer_bytes": n * 4}
+    for name, op, moved in (("copy", lambda: b.copy_(a), 2 * n * 4), ("inplace_rmw", lambda: a.neg_(), 2 * n * 4)):
+        for _ in range(3):
+            op()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            op()
+        e1.record()
+        e1.synchronize()
+        res[f"{name}_gbs"] = moved / (e0.elapsed_time(e1) / 10 * 1e-3) / 1e9
+    res["halfsweep_over_copy"] = achieved_gbs / res["copy_gbs"]
+    res["halfsweep_over_inplace_rmw"] = achieved_gbs / res["inplace_rmw_gbs"]
+    del a, b
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_diff(gf, synth, torch):
     """Differentiation line: F_U[g] and its hand-written backward at 24^4
     (amp 0.4, s_a ~ N(0, 0.1^2)), FP32 and FP64; 20 timed calls each."""
@@ -280,6 +306,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation timing leg")
     ap.add_argument("--no-sun", action="store_true", help="skip the SU(2) / SU(4) leg")
+    ap.add_argument("--no-bw-reference", action="store_true",
+                    help="skip the device copy / in-place read-modify-write bandwidth reference")
     ap.add_argument("--workload", choices=["single", "ensemble", "sun", "sd", "diff"], default="single",
                     help="ensemble: Coulomb 48^3x96 plus 64 Landau lattices of uneven volume fixed together; "
                          "sun: only the SU(2) / SU(4) leg; sd: only steepest descent with Fourier acceleration; "
@@ -520,6 +548,10 @@ def main():
 
     if not args.no_sun:
         out["sun"] = run_sun(args, dims, gf, synth, torch)
+
+    if not args.no_bw_reference:
+        log("HBM reference: device copy and in-place read-modify-write of a field-sized buffer")
+        out["bandwidth_reference"] = bw_reference(torch, rf32["bytes_per_launch"] // 2, rf32["achieved_gbs"])
 
     if args.copy_probe:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
