@@ -29,7 +29,10 @@ namespace gf {
 
 namespace {
 
-struct Cd {
+// 16-byte aligned so that a value moves to and from LDS as one 128-bit
+// access: as two 64-bit halves, consecutive lanes' values fell into the same
+// banks and every LDS instruction of the transforms stalled on conflicts.
+struct alignas(16) Cd {
     double x, y;
 };
 
