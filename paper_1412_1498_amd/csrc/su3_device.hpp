@@ -107,9 +107,14 @@ __device__ __forceinline__ void store_link(const Mat<R> &m, gchar *base, long lo
     } else {
 #pragma unroll
         for (int e = 0; e < NE; e++) {
+            R x = m.re[e], y = m.im[e];
+            // keep the pair as two register values: otherwise the compiler may
+            // fetch re[e] together with its neighbour re[e + 1] as one 8-byte
+            // load, which keeps m in memory (LDS) instead of registers
+            asm("" : "+v"(x), "+v"(y));
             v2 v;
-            v.x = m.re[e];
-            v.y = m.im[e];
+            v.x = x;
+            v.y = y;
             st<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)), v);
         }
     }
