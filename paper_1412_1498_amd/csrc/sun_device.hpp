@@ -33,9 +33,11 @@ __device__ __forceinline__ void store_link_n(const MatN<R, N> &m, gchar *base, l
     gchar *p = base + off * (long long)sizeof(v2);
 #pragma unroll
     for (int e = 0; e < N * N; e++) {
+        R x = m.re[e], y = m.im[e];
+        asm("" : "+v"(x), "+v"(y));  // as in store_link: keeps m in registers
         v2 v;
-        v.x = m.re[e];
-        v.y = m.im[e];
+        v.x = x;
+        v.y = y;
         st<NT, v2>(p, (uint32_t)(e * BLK * sizeof(v2)), v);
     }
 }
