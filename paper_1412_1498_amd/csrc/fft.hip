@@ -409,20 +409,24 @@ k_sd_fx_gfield(Geom g, FftSite f, const Cd *__restrict__ Wg, const typename V2<R
     const long long sr0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.ys;
     row_info(ri, g, sr0, f.ys, f.srows);
     __syncthreads();
+    // Every lane loads unconditionally (a pair that does not exist reads
+    // element 0 and is zeroed afterwards): loads under a branch made the
+    // compiler copy each result at the branch's end, which waited for it, so
+    // only two loads were ever in flight.
     typename V2<R>::type va[LOAD_C], vb[LOAD_C];
+    bool ok[LOAD_C];
 #pragma unroll
     for (int i = 0; i < LOAD_C; i++) {  // nc nkx <= FFT_TILE_POINTS (pencil, frequency) pairs
         const int idx = threadIdx.x + i * FFT_BLOCK;
-        va[i].x = va[i].y = vb[i].x = vb[i].y = (R)0;
-        if (idx < nc * f.nkx) {
-            const int cr = (int)fdiv((unsigned)idx, f.dnkx), k = idx - cr * f.nkx;
-            const RowInfo r = ri[cr >> 2];
-            if (r.zy >= 0) {
-                const int a = 2 * (cr & 3);
-                va[i] = spec[spec_index(g, f.nkx, r, a, k)];
-                vb[i] = spec[spec_index(g, f.nkx, r, a + 1, k)];
-            }
-        }
+        const bool in = idx < nc * f.nkx;
+        const int cr = in ? (int)fdiv((unsigned)idx, f.dnkx) : 0, k = idx - cr * f.nkx;
+        const RowInfo r = ri[cr >> 2];
+        ok[i] = in && r.zy >= 0;
+        const int a = 2 * (cr & 3);
+        const long long ia = ok[i] ? spec_index(g, f.nkx, r, a, k) : 0;
+        const long long ib = ok[i] ? spec_index(g, f.nkx, r, a + 1, k) : 0;
+        va[i] = spec[ia];
+        vb[i] = spec[ib];
     }
     load_roots(t, Wg, nx);
 #pragma unroll
@@ -430,7 +434,8 @@ k_sd_fx_gfield(Geom g, FftSite f, const Cd *__restrict__ Wg, const typename V2<R
         const int idx = threadIdx.x + i * FFT_BLOCK;
         if (idx >= nc * f.nkx) continue;
         const int cr = (int)fdiv((unsigned)idx, f.dnkx), k = idx - cr * f.nkx;
-        const Cd A = Cd{(double)va[i].x, (double)va[i].y}, B = Cd{(double)vb[i].x, (double)vb[i].y};
+        const double z = ok[i] ? 1.0 : 0.0;
+        const Cd A = Cd{z * (double)va[i].x, z * (double)va[i].y}, B = Cd{z * (double)vb[i].x, z * (double)vb[i].y};
         if (k == 0 || k == h) {
             t.a[k * t.ld + cr] = Cd{A.x, B.x};
         } else {
