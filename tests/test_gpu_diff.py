@@ -172,3 +172,67 @@ def test_sd_cross_check_large(gf, field_cache, dims, prec):
     Fs += sd_run_gpu(ctx, Ug, sg0, 198, 0.08)[1:]
     assert np.all(np.diff(Fs) > (-1e-15 if prec == 0 else -2e-7))
     assert Fs[-1] > Fs[0]
+
+
+def _expm_site(s_x):
+    import scipy.linalg
+    return scipy.linalg.expm(1j * np.tensordot(s_x, diff.LAMBDA, axes=1) / 2)
+
+
+def _local_staple(U, s, site, gauge):
+    """K(x) of eq. (5) at one site for g = expm(i s lambda / 2), from scipy's
+    expm of the neighbours' s (independent of the oracle's eigh route):
+    sum over mu in D of U_mu(x) g(x+mu)^+ + U_mu(x-mu)^+ g(x-mu)^+."""
+    t, z, y, x = site
+    n = U.shape[:4]
+    K = np.zeros((3, 3), dtype=np.complex128)
+    for mu in range(3 if gauge == COULOMB else 4):
+        step = [0, 0, 0, 0]
+        step[3 - mu] = 1
+        fwd = tuple((c + d) % L for c, d, L in zip(site, step, n))
+        bwd = tuple((c - d) % L for c, d, L in zip(site, step, n))
+        K += U[t, z, y, x, mu] @ _expm_site(s[fwd]).conj().T
+        K += U[bwd][mu].conj().T @ _expm_site(s[bwd]).conj().T
+    return K
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("dims", [(16, 16, 16, 16), (24, 24, 24, 24)])
+def test_gradient_central_differences_256_pairs(gf, dims, prec):
+    """Amp 0.4 (seed 0), s ~ N(0, 0.1) (seed 1): the backward kernel at 256
+    random (x, a) pairs against central differences (step 1e-6, FP64) of the
+    local functional f_x(s) = Re Tr[g(x) K(x)], the only part of eq. (1) that
+    depends on s(x) (eqs. 4-5), divided by d N_c V. FP64: 1e-8 relative to
+    max(|difference|, 5% of the largest entry) -- the quotient itself rounds
+    by ~1e-16 |f_x| / h, about 1e-10 of the largest entry, which would swamp
+    a plain relative bound on entries near zero. FP32: the kernel rounds U, s
+    and g to float (6e-8 each on O(10) terms), measured 3e-8 of the largest
+    entry, bound 2e-7."""
+    from paper_1412_1498_amd import synth
+    U = synth.random_gauge_field(dims, 0.4, 0).numpy()
+    s = synth.random_algebra_field(dims, 0.1, 1).numpy()
+    ctx, Ug, sg = setup(gf, dims, LANDAU, prec, U, s)
+    Uo, so = cast(U, s, prec)
+    grad = ctx.unpack_alg(ctx.functional_grad(Ug, sg)).cpu().numpy().astype(np.float64)
+    V = int(np.prod(dims))
+    scale = np.abs(grad).max()
+    rng = np.random.default_rng(2)
+    h = 1e-6
+    worst = 0.0
+    for _ in range(256):
+        site = tuple(int(rng.integers(L)) for L in (dims[3], dims[2], dims[1], dims[0]))
+        a = int(rng.integers(8))
+        K = _local_staple(Uo, so, site, LANDAU)
+        vals = []
+        for sign in (+1, -1):
+            sp = so[site].copy()
+            sp[a] += sign * h
+            vals.append(np.trace(_expm_site(sp) @ K).real)
+        fd = (vals[0] - vals[1]) / (2 * h) / (4 * 3 * V)
+        g = grad[site + (a,)]
+        if prec == 0:
+            worst = max(worst, abs(fd - g) / max(abs(fd), 0.05 * scale))
+        else:
+            worst = max(worst, abs(fd - g) / scale)
+    print(f"{dims} prec {prec}: worst {worst:.2e}")
+    assert worst < (1e-8 if prec == 0 else 2e-7)

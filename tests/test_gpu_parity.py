@@ -180,10 +180,14 @@ def test_fix_matches_oracle_fp64(gf, oracle_lib, field_cache, gauge):
     ro = oracle_lib.fix(Uo, dims, 1.7, 1e-12, 2000, gauge, reunit_every=20)
     assert r["converged"] and ro["converged"]
     assert r["theta"] < 1e-12
-    assert abs(r["iters"] - ro["iters"]) <= 1
-    assert abs(r["F"] - ro["F"]) < 1e-12
-    if r["iters"] == ro["iters"]:
-        assert np.abs(to_host(ctx, Ug) - Uo).max() < 1e-11
+    # Same stopping sweep (the check/stop logic of Alg. 1), same F, theta and
+    # the same gauge-fixed field.
+    assert r["iters"] == ro["iters"], (r, ro)
+    assert abs(r["F"] - ro["F"]) < 1e-13
+    assert abs(r["theta"] - ro["theta"]) < 1e-3 * ro["theta"]
+    err = np.abs(to_host(ctx, Ug) - Uo).max()
+    print(f"gauge {gauge}: iters {r['iters']}, max|dU| {err:.2e}")
+    assert err < 1e-12
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -435,7 +439,9 @@ def test_precision_line_32x4(gf, oracle_lib):
     # differences in b are amplified ~1/|b| in g; over 10^6 sites a few such
     # sites show up, so the bound is on the distribution and on the maximum.
     err = np.abs(to_host(c64, U64) - Uo)
-    assert np.median(err) < 5e-15 and np.quantile(err, 0.999) < 1e-13 and err.max() < 1e-11
+    print(f"32^4 FP64 two sweeps: median {np.median(err):.2e}, q99.9 {np.quantile(err, 0.999):.2e}, "
+          f"max {err.max():.2e}")
+    assert np.median(err) < 5e-15 and np.quantile(err, 0.999) < 5e-14 and err.max() < 1e-12
     c64.sweep_count = 0
     U64 = c64.pack(U)
     r64 = c64.fix(U64, 1.7, 1e-12, 20000)

@@ -132,15 +132,21 @@ def test_all_schedules_give_identical_bits(gf, n, prec):
 @pytest.mark.parametrize("n", [2, 4])
 @pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
 def test_fix_matches_oracle_fp64(gf, n, gauge):
-    """Alg. 1 to theta < 1e-12 with reunitarisation every 4 sweeps: same
-    sweep count (+-1: theta near the threshold) and F within 1e-12."""
+    """Alg. 1 to theta < 1e-12 with reunitarisation every 4 sweeps: the same
+    stopping sweep, F and gauge-fixed field as the oracle."""
     dims = (4, 4, 4, 4)
     U = field(dims, n, 0.3, 5)
     ctx = ctx_of(gf, dims, n, gauge, 0, reunit_every=4)
-    r = ctx.fix(to_gpu(ctx, U), 1.7, 1e-12, 3000)
-    ro = sun.fix(U.copy(), dims, 1.7, 1e-12, 3000, gauge, reunit_every=4)
+    Ug = to_gpu(ctx, U)
+    r = ctx.fix(Ug, 1.7, 1e-12, 3000)
+    Uo = U.copy()
+    ro = sun.fix(Uo, dims, 1.7, 1e-12, 3000, gauge, reunit_every=4)
     assert r["converged"] and ro["converged"]
-    assert abs(r["iters"] - ro["iters"]) <= 1 and abs(r["F"] - ro["F"]) < 1e-12
+    assert r["iters"] == ro["iters"], (r, ro)
+    assert abs(r["F"] - ro["F"]) < 1e-13
+    err = np.abs(to_host(ctx, Ug) - Uo).max()
+    print(f"SU({n}) gauge {gauge}: iters {r['iters']}, max|dU| {err:.2e}")
+    assert err < 1e-12
 
 
 @pytest.mark.parametrize("n", [2, 4])

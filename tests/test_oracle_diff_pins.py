@@ -96,3 +96,63 @@ def test_sd_steps_increase_F(oracle_lib, field_cache):
         U = np.ascontiguousarray(diff.sd_step(U, 0.08))
         F.append(oracle_lib.quality(U, dims, 0)[0])
     assert np.all(np.diff(F) > 0)
+
+
+def _textbook_gell_mann():
+    """The eight Gell-Mann matrices written out, kept apart from the oracle's
+    own table so that a slip in either shows up."""
+    i = 1j
+    r3 = 1 / np.sqrt(3)
+    return np.array([
+        [[0, 1, 0], [1, 0, 0], [0, 0, 0]],
+        [[0, -i, 0], [i, 0, 0], [0, 0, 0]],
+        [[1, 0, 0], [0, -1, 0], [0, 0, 0]],
+        [[0, 0, 1], [0, 0, 0], [1, 0, 0]],
+        [[0, 0, -i], [0, 0, 0], [i, 0, 0]],
+        [[0, 0, 0], [0, 0, 1], [0, 1, 0]],
+        [[0, 0, 0], [0, 0, -i], [0, i, 0]],
+        [[r3, 0, 0], [0, r3, 0], [0, 0, -2 * r3]],
+    ], dtype=np.complex128)
+
+
+def _global_sum(oracle_lib, U, s, dims, gauge, lam):
+    """d N_c V F_U[g] (eq. 1) for g(x) = expm(i sum_a s_a lambda_a / 2), built
+    without oracle/diff.py: scipy's expm per site, the transformed links by
+    plain products, and F from the C oracle."""
+    nd = 3 if gauge == COULOMB else 4
+    V = int(np.prod(dims))
+    g = np.empty(s.shape[:4] + (3, 3), dtype=np.complex128)
+    for idx in np.ndindex(*s.shape[:4]):
+        g[idx] = scipy.linalg.expm(1j * np.tensordot(s[idx], lam, axes=1) / 2)
+    Ut = np.empty_like(U)
+    for mu in range(4):
+        gfwd = np.roll(g, -1, axis=3 - mu)
+        Ut[..., mu, :, :] = g @ U[..., mu, :, :] @ np.conj(np.swapaxes(gfwd, -1, -2))
+    return oracle_lib.quality(np.ascontiguousarray(Ut), dims, gauge)[0] * nd * 3 * V
+
+
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+def test_gradient_at_nonzero_s_matches_the_global_functional(oracle_lib, field_cache, gauge):
+    """dF/ds_a(x) at s != 0 (sigma 0.3) for every (x, a) of a V = 32 lattice,
+    against a fourth-order central difference (step 1e-3) of the whole
+    functional F_U[g] of eq. (1) evaluated through the C oracle. The
+    difference's truncation error is O(h^4) ~ 1e-13 and its rounding error
+    ~1e-16 d N_c V / h ~ 1e-11 of an O(1) derivative of the unnormalised sum."""
+    lam = _textbook_gell_mann()
+    dims = (2, 4, 2, 2)
+    U = field_cache(dims, 0.5, 27)
+    s = rand_alg(dims, 0.3, 28)
+    V = int(np.prod(dims))
+    nd = 3 if gauge == COULOMB else 4
+    grad = diff.gradient(U, s, gauge) * nd * 3 * V
+    h = 1e-3
+    worst = 0.0
+    for idx in np.ndindex(*s.shape):
+        vals = {}
+        for k in (-2, -1, 1, 2):
+            sp = s.copy()
+            sp[idx] += k * h
+            vals[k] = _global_sum(oracle_lib, U, sp, dims, gauge, lam)
+        fd = (8 * (vals[1] - vals[-1]) - (vals[2] - vals[-2])) / (12 * h)
+        worst = max(worst, abs(fd - grad[idx]) / max(1e-2, abs(grad[idx])))
+    assert worst < 1e-8, worst
