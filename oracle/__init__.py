@@ -15,6 +15,6 @@ nothing from it.
 from .core import (  # noqa: F401
     build, load, quality, divergence_field, staple, su2_solve,
     subgroup_update, site_update, half_sweep, half_sweep_order, sweep,
-    reunit, fix, parity_of_sites,
+    reunit, fix, parity_of_sites, set_threads,
 )
 from . import sun  # noqa: F401

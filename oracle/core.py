@@ -22,10 +22,11 @@ LANDAU, COULOMB = 0, 1
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no FP contraction)."""
+    """Compile the oracle with gcc (plain -O2, no FP contraction; OpenMP
+    shares the sites of a half-sweep among threads)."""
     if force or not os.path.exists(_LIB) or any(os.path.getmtime(_LIB) < os.path.getmtime(f) for f in _SRCS):
         tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-std=c99",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c99",
                                "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -50,6 +51,8 @@ def load():
         lib.oracle_reunit.argtypes = [P, L]
         lib.oracle_fix.argtypes = [P, P, I, D, D, I, I, I, L, P, P, P]
         lib.oracle_fix.restype = I
+        lib.oracle_set_threads.argtypes = [I]
+        lib.oracle_set_threads.restype = I
         lib.oracle_sun_quality.argtypes = [P, P, I, I, P, P]
         lib.oracle_sun_staple.argtypes = [P, P, I, I, L, P]
         lib.oracle_sun_subgroup_matrix.argtypes = [P, P, I, I, L, I, I, D, P]
@@ -152,6 +155,12 @@ def fix(U, dims, omega, eps, max_iter, gauge=LANDAU, reunit_every=20, check_ever
                              int(max_iter), int(reunit_every), int(check_every), int(start_sweep),
                              ctypes.byref(it), ctypes.byref(F), ctypes.byref(th))
     return dict(converged=bool(conv), iters=it.value, F=F.value, theta=th.value)
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads shared by the sites of a half-sweep (n <= 0: keep the current
+    number). Returns the number in effect."""
+    return int(load().oracle_set_threads(int(n)))
 
 
 def parity_of_sites(dims):

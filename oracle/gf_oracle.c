@@ -28,11 +28,14 @@
  *    (d = 4 Landau, d = 3 Coulomb), so F = 1 on the unit field.
  *  - reunitarisation is Gram-Schmidt on rows 0 and 1, row 2 = conj(r0 x r1).
  *
- * Build: gcc -O2 -ffp-contract=off -fPIC -shared -std=c99 -o liboracle.so gf_oracle.c -lm
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared -std=c99 -o liboracle.so gf_oracle.c -lm
  */
 #include <complex.h>
 #include <math.h>
 #include <stdlib.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef double complex cplx;
 typedef struct { cplx m[3][3]; } mat3;
@@ -243,14 +246,30 @@ void oracle_site_update(cplx *U, const int d[4], int gauge, long s, double omega
     for (int sub = 0; sub < 3; sub++) oracle_subgroup_update(U, d, gauge, s, sub, omega);
 }
 
-/* Alg. 1, inner loops for one site parity: every site of that parity, in
- * lexicographic order (the order does not matter, same-parity sites share no
- * link). */
+/* Alg. 1, inner loops for one site parity: every site of that parity. The
+ * order does not matter: a site reads and writes only the eight links
+ * U_mu(x), U_mu(x - mu) that touch it, and no two sites of one parity touch
+ * the same link, so the sites may also be shared among threads (OpenMP,
+ * when built with it) with a result that does not depend on their number. */
 void oracle_half_sweep(cplx *U, const int d[4], int gauge, int parity, double omega)
 {
     long V = volume(d);
+#pragma omp parallel for schedule(static)
     for (long s = 0; s < V; s++)
         if (parity_of(d, s) == parity) oracle_site_update(U, d, gauge, s, omega);
+}
+
+/* Threads used by oracle_half_sweep (1 when built without OpenMP). n <= 0
+ * leaves the current setting. Returns the number in effect. */
+int oracle_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
 }
 
 /* Same, but visiting the sites of that parity in a caller-given order

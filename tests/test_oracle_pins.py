@@ -277,6 +277,34 @@ def test_half_sweep_is_independent_of_site_order(oracle_lib, field_cache):
         np.testing.assert_array_equal(A, B)
 
 
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+def test_sweeps_do_not_depend_on_the_thread_count(oracle_lib, field_cache, gauge):
+    """The threaded half-sweep (the CPU baseline's timed form) gives bitwise
+    the single-thread result, and both equal the sequential lexicographic
+    visit of half_sweep_order."""
+    import os
+    dims = (6, 4, 4, 8)
+    U = field_cache(dims, 0.7, 9)
+    V = int(np.prod(dims))
+    before = oracle_lib.set_threads(0)
+    try:
+        out = []
+        for n in (1, max(2, os.cpu_count() or 2)):
+            assert oracle_lib.set_threads(n) == n
+            A = U.copy()
+            for _ in range(3):
+                oracle_lib.sweep(A, dims, 1.7, gauge)
+            out.append(A)
+        B = U.copy()
+        for _ in range(3):
+            for p in (0, 1):
+                oracle_lib.half_sweep_order(B, dims, p, 1.7, np.arange(V), gauge)
+        np.testing.assert_array_equal(out[0], out[1])
+        np.testing.assert_array_equal(out[0], B)
+    finally:
+        oracle_lib.set_threads(before)
+
+
 # --- F and theta, eqs. (1)-(3) ----------------------------------------------
 
 @pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
