@@ -113,6 +113,19 @@ typedef struct gf_params {
                                (SU(2)/SU(4) kernels always stream) */
     int use_graph;          /* 1 = replay each check period as a hipGraph */
     int timing;             /* 1 = time every half-sweep with hipEvents */
+    const char *log_path;   /* NULL = no log. Else the fix drivers (gf_fix,
+                               gf_batch_fix, gf_sd_fix) append one JSON object
+                               per line and per member at every F/theta
+                               evaluation, the initial one included:
+                               {"driver": "alg1" | "alg2", "call": k,
+                                "member": i, "sweep" | "step": n, "F": F,
+                                "theta": theta, "elapsed_s": s}, with k the
+                               driver call's number in the context, n the
+                               member's sweeps (Alg. 1) or steps (Alg. 2) so
+                               far in that call and s the seconds since it
+                               began. The context copies the path at creation
+                               and opens the file (append) on first use;
+                               flushed after every check. */
 } gf_params;
 
 /* Fill *p with the defaults for precision prec. */
@@ -136,14 +149,19 @@ int gf_create(gf_ctx **out, const int dims[4], int nc, int gauge, int prec, void
 int gf_batch_create(gf_ctx **out, int n, const int *dims, const int *gauge, int prec, void *stream,
                     const gf_params *p);
 
-/* Release a context (waits for its stream). NULL is accepted. */
+/* Release a context (waits for its stream, closes its log). NULL is
+ * accepted. gf_batch_destroy is the same call under the ensemble's name:
+ * single lattices and ensembles share the context type. */
 int gf_destroy(gf_ctx *ctx);
+int gf_batch_destroy(gf_ctx *ctx);
 
 /* Human-readable description of the last error on ctx ("" if none). */
 const char *gf_last_error(const gf_ctx *ctx);
 
 /* Bytes of one field of member i in the internal layout:
- * 2 * nb * 4 * ne * 64 * sizeof(complex) (padding included). */
+ * 2 * nb * 4 * ne * 64 * sizeof(complex) (padding included). Members of an
+ * ensemble differ in size, hence the member index; 0 for a single lattice.
+ * Returns 0 for a NULL context or a member out of range. */
 size_t gf_field_bytes(const gf_ctx *ctx, int member);
 
 /* Convert member 0's field between the canonical layout U_aos (device) and
@@ -171,6 +189,17 @@ int gf_reunit(gf_ctx *ctx, void *U);
  * Synchronises the stream. Returns GF_ENONFINITE if either is NaN or Inf. */
 int gf_quality(gf_ctx *ctx, const void *U, double *F, double *theta);
 
+/* Per time slice t = 0 .. nt-1 of member 0 (SU(3)): F_t and theta_t, the
+ * sums of eqs. (1)-(2) over the nx ny nz sites of slice t normalised by
+ * that slice volume (F_t by d N_c V_t, theta_t by N_c V_t), so that the mean
+ * over t of theta_t is theta and that of F_t is F. For the Coulomb gauge
+ * (Delta from the spatial links, one global theta gating convergence) this
+ * is the per-slice diagnostic; it is defined for Landau too. F_t and theta_t
+ * are host arrays of nt doubles. The first call allocates
+ * 2 nt ceil(nx ny nz / 256) + 2 nt doubles of scratch (kept by the context).
+ * Synchronises. GF_ENONFINITE if a value is NaN or Inf. */
+int gf_quality_slices(gf_ctx *ctx, const void *U, double *F_t, double *theta_t);
+
 /* Alg. 1 on member 0: compute F, theta; while theta >= eps and fewer than
  * max_iter sweeps were done: sweep (with scheduled reunitarisation) and
  * recompute F, theta every check_every sweeps and after the last allowed
@@ -194,9 +223,12 @@ int gf_batch_quality(gf_ctx *ctx, void *const *U, double *F, double *theta);
 /* Time the candidate schedules (lanes per site, workgroup size,
  * non-temporal access) on a scratch copy of the members' fields U[i] and
  * keep the fastest in ctx. Every schedule gives bitwise the same links. If
- * cache_path is not NULL, a previous result for the same device, precision,
- * storage and lattice list is reused and new results are appended.
- * Allocates (and frees) a scratch copy of the fields. Synchronises. */
+ * cache_path is not NULL, a previous result for the same device, library
+ * sources, colour number, precision, storage and lattice list is reused and
+ * new results are appended. The context itself (single lattice or
+ * ensemble) is the first argument, and the fields to time on and omega are
+ * passed explicitly, because the timing runs real half-sweeps. Allocates
+ * (and frees) a scratch copy of the fields. Synchronises. */
 int gf_autotune(gf_ctx *ctx, void *const *U, double omega, const char *cache_path);
 
 /* The schedule in use: lanes per site, workgroup threads and the

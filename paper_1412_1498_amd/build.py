@@ -7,6 +7,7 @@ instructions are disabled for all device code.
 from __future__ import annotations
 
 import concurrent.futures as cf
+import hashlib
 import os
 import subprocess
 import sys
@@ -43,8 +44,20 @@ def _compile(src: str, extra=()) -> str:
     return obj
 
 
+def source_hash() -> str:
+    """sha256 (16 hex digits) of every file under csrc/ and include/."""
+    h = hashlib.sha256()
+    for d in (CSRC, os.path.join(ROOT, "include")):
+        for f in sorted(os.listdir(d)):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode())
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, extra=()) -> str:
     os.makedirs(BUILD, exist_ok=True)
+    extra = [*extra, f'-DGF_SOURCE_HASH="{source_hash()}"']
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra), SOURCES))
     tmp = OUT + f".tmp{os.getpid()}"

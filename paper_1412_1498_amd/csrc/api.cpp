@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -24,6 +25,12 @@
 #include "sun_internal.hpp"
 
 using namespace gf;
+
+// Hash of the library's sources, set by the build; keys autotuner cache
+// entries so that a schedule measured on other kernels is not reused.
+#ifndef GF_SOURCE_HASH
+#define GF_SOURCE_HASH "unknown"
+#endif
 
 struct gf_ctx {
     int n = 0;
@@ -67,6 +74,13 @@ struct gf_ctx {
     // and t lengths (FFT_MAX_N complex doubles each)
     void *d_spec = nullptr;
     void *d_roots = nullptr;
+    // per-time-slice quality: partials and results
+    double *d_slice_part = nullptr;
+    double *d_slice_out = nullptr;
+    // per-check JSON-lines log of the fix drivers (gf_params.log_path)
+    std::string log_path;
+    FILE *log = nullptr;
+    long long log_calls = 0;
 };
 
 namespace {
@@ -94,6 +108,32 @@ int fail(gf_ctx *ctx, int code, const char *fmt, ...) {
     do {                                                                                         \
         if (!(cond)) return fail(ctx, code, __VA_ARGS__);                                        \
     } while (0)
+
+// ---- per-check log (gf_params.log_path) ----------------------------------
+// One JSON object per line and per member at every F/theta evaluation of a
+// fix driver: the driver ("alg1" overrelaxation, "alg2" Fourier-accelerated
+// steepest descent), the driver call's number within the context, the
+// member, its sweeps (steps) so far in this call, F, theta and the seconds
+// since the call began. Appended to the file, flushed after every check.
+using Clock = std::chrono::steady_clock;
+
+void log_open(gf_ctx *ctx) {
+    if (!ctx->log && !ctx->log_path.empty()) ctx->log = std::fopen(ctx->log_path.c_str(), "a");
+}
+
+void log_check(gf_ctx *ctx, bool sd, int member, long long iters, double F, double theta,
+               Clock::time_point t0) {
+    if (!ctx->log) return;
+    const double el = std::chrono::duration<double>(Clock::now() - t0).count();
+    std::fprintf(ctx->log,
+                 "{\"driver\": \"%s\", \"call\": %lld, \"member\": %d, \"%s\": %lld, \"F\": %.17g, "
+                 "\"theta\": %.17g, \"elapsed_s\": %.9f}\n",
+                 sd ? "alg2" : "alg1", ctx->log_calls, member, sd ? "step" : "sweep", iters, F, theta, el);
+}
+
+void log_flush(gf_ctx *ctx) {
+    if (ctx->log) std::fflush(ctx->log);
+}
 
 // Make the context's device current for the duration of a call.
 struct DeviceGuard {
@@ -311,6 +351,8 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
     ctx->p = p;
     ctx->sched = s;
     ctx->sweeps_done = p.start_sweep;
+    if (p.log_path) ctx->log_path = p.log_path;
+    ctx->p.log_path = nullptr;  // the context keeps its own copy
     int rc = GF_OK;
     auto bail = [&](int code) { gf_destroy(ctx); return code; };
     if (hipGetDevice(&ctx->device) != hipSuccess) return bail(GF_EDEVICE);
@@ -422,9 +464,14 @@ int gf_destroy(gf_ctx *ctx) {
     if (ctx->h_stage) (void)hipHostFree(ctx->h_stage);
     if (ctx->h_result) (void)hipHostFree(ctx->h_result);
     if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+    (void)hipFree(ctx->d_slice_part);
+    (void)hipFree(ctx->d_slice_out);
+    if (ctx->log) std::fclose(ctx->log);
     delete ctx;
     return GF_OK;
 }
+
+int gf_batch_destroy(gf_ctx *ctx) { return gf_destroy(ctx); }
 
 const char *gf_last_error(const gf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -523,6 +570,41 @@ int gf_quality(gf_ctx *ctx, const void *U, double *F, double *theta) {
     return gf_batch_quality(ctx, &u, F, theta);
 }
 
+int gf_quality_slices(gf_ctx *ctx, const void *U, double *F_t, double *theta_t) {
+    if (!ctx) return GF_EINVAL;
+    int rc;
+    if ((rc = need_single(ctx)) || (rc = need_su3(ctx)) || (rc = check_field(ctx, U, "U"))) return rc;
+    CHECK(ctx, F_t && theta_t, GF_EINVAL, "NULL argument");
+    DeviceGuard dg(ctx->device);
+    const Geom &g = ctx->desc[0].g;
+    if (!ctx->d_slice_part) {
+        const size_t np = 2 * (size_t)g.nt * quality_slice_chunks(g);
+        if (hipMalloc(&ctx->d_slice_part, np * sizeof(double)) != hipSuccess) {
+            ctx->d_slice_part = nullptr;
+            return fail(ctx, GF_ENOMEM, "cannot allocate the per-slice partials");
+        }
+    }
+    if (!ctx->d_slice_out && hipMalloc(&ctx->d_slice_out, 2 * (size_t)g.nt * sizeof(double)) != hipSuccess) {
+        ctx->d_slice_out = nullptr;
+        return fail(ctx, GF_ENOMEM, "cannot allocate the per-slice results");
+    }
+    CfgDesc d = ctx->desc[0];
+    d.U = const_cast<void *>(U);
+    HIPTRY(ctx, launch_quality_slices(ctx->prec, ctx->nelem, d, ctx->d_slice_part, ctx->d_slice_out, ctx->stream));
+    std::vector<double> h(2 * (size_t)g.nt);
+    HIPTRY(ctx, hipMemcpyAsync(h.data(), ctx->d_slice_out, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream));
+    HIPTRY(ctx, hipStreamSynchronize(ctx->stream));
+    bool bad = false;
+    for (int t = 0; t < g.nt; t++) {
+        F_t[t] = h[2 * t];
+        theta_t[t] = h[2 * t + 1];
+        if (!std::isfinite(F_t[t]) || !std::isfinite(theta_t[t])) bad = true;
+    }
+    if (bad) return fail(ctx, GF_ENONFINITE, "a slice's F or theta is not finite");
+    return GF_OK;
+}
+
 int gf_fix(gf_ctx *ctx, void *U, double omega, double eps, int max_iter, int *iters, double *F,
            double *theta) {
     if (!ctx) return GF_EINVAL;
@@ -544,12 +626,26 @@ int gf_batch_fix(gf_ctx *ctx, void *const *U, const double *omega, double eps, i
     DeviceGuard dg(ctx->device);
     if ((rc = set_fields(ctx, U, omega))) return rc;
     const int n = ctx->n;
+    const Clock::time_point t0 = Clock::now();
+    log_open(ctx);
+    ctx->log_calls++;
     // every member starts active with zero sweeps
     for (int c = 0; c < n; c++) { ctx->h_flags[c] = 1; ctx->h_flags[n + c] = 0; }
     HIPTRY(ctx, hipMemcpyAsync(ctx->d_active, ctx->h_flags, n * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
     HIPTRY(ctx, hipMemcpyAsync(ctx->d_iters, ctx->h_flags + n, n * sizeof(int), hipMemcpyHostToDevice, ctx->stream));
     if ((rc = quality_launch(ctx, ctx->d_active, 1, 0, eps, ctx->stream))) return rc;
     if ((rc = read_back(ctx, true))) return rc;
+    // members active before a check (those whose result it refreshed)
+    std::vector<int> was_active(n, 1);
+    auto log_members = [&]() {
+        if (!ctx->log) return;
+        for (int c = 0; c < n; c++)
+            if (was_active[c])
+                log_check(ctx, false, c, ctx->h_flags[n + c], ctx->h_result[2 * c], ctx->h_result[2 * c + 1], t0);
+        log_flush(ctx);
+        for (int c = 0; c < n; c++) was_active[c] = ctx->h_flags[c];
+    };
+    log_members();
     const bool graphs = ctx->p.use_graph && !ctx->p.timing && ctx->p.check_every <= 64;
     int it = 0;
     auto any_active = [&]() {
@@ -593,6 +689,7 @@ int gf_batch_fix(gf_ctx *ctx, void *const *U, const double *omega, double eps, i
         }
         it += m;
         if ((rc = read_back(ctx, true))) return rc;
+        log_members();
     }
     bool all = true;
     for (int c = 0; c < n; c++) {
@@ -652,7 +749,8 @@ int gf_autotune(gf_ctx *ctx, void *const *U, double omega, const char *cache_pat
     hipDeviceProp_t prop;
     HIPTRY(ctx, hipGetDeviceProperties(&prop, ctx->device));
     std::ostringstream key;
-    key << prop.gcnArchName << "|cu" << prop.multiProcessorCount << "|p" << ctx->prec << "|e" << ctx->nelem;
+    key << prop.gcnArchName << "|cu" << prop.multiProcessorCount << "|src" << GF_SOURCE_HASH << "|n" << ctx->nc
+        << "|p" << ctx->prec << "|e" << ctx->nelem;
     for (int c = 0; c < ctx->n; c++) {
         const Geom &g = ctx->desc[c].g;
         key << "|" << g.nx << "x" << g.ny << "x" << g.nz << "x" << g.nt << "g" << ctx->desc[c].gauge;
@@ -937,8 +1035,13 @@ int gf_sd_fix(gf_ctx *ctx, void *U, double alpha, double eps, int max_iter, int 
     CHECK(ctx, max_iter >= 0, GF_EINVAL, "max_iter must be >= 0");
     DeviceGuard dg(ctx->device);
     if ((rc = sd_prepare(ctx))) return rc;
+    const Clock::time_point t0 = Clock::now();
+    log_open(ctx);
+    ctx->log_calls++;
     *iters = 0;
     if ((rc = gf_quality(ctx, U, F, theta))) return rc;
+    log_check(ctx, true, 0, 0, *F, *theta, t0);
+    log_flush(ctx);
     int it = 0;
     while (it < max_iter && !(*theta < eps)) {
         const int m = std::min(ctx->p.check_every, max_iter - it);
@@ -947,6 +1050,8 @@ int gf_sd_fix(gf_ctx *ctx, void *U, double alpha, double eps, int max_iter, int 
         it += m;
         *iters = it;
         if ((rc = gf_quality(ctx, U, F, theta))) return rc;
+        log_check(ctx, true, 0, it, *F, *theta, t0);
+        log_flush(ctx);
     }
     return *theta < eps ? GF_OK : GF_NOT_CONVERGED;
 }

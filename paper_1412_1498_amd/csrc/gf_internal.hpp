@@ -128,6 +128,11 @@ hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int 
 hipError_t launch_quality_final(const CfgDesc *d_desc, int n, const double *d_partials,
                                 double *d_result, int *d_active, int *d_iters, int swept,
                                 double eps, int update_active, hipStream_t st);
+// Per-time-slice F_t and theta_t of one member into d_out[2 t], d_out[2 t + 1];
+// d_partials holds 2 * nt * quality_slice_chunks(g) doubles.
+int quality_slice_chunks(const Geom &g);
+hipError_t launch_quality_slices(int prec, int nelem, const CfgDesc &d, double *d_partials, double *d_out,
+                                 hipStream_t st);
 hipError_t launch_pack(int prec, int nelem, const Geom &g, const void *aos, void *U, int unpack,
                        hipStream_t st);
 hipError_t launch_reunit(int prec, int nelem, const Geom &g, void *U, hipStream_t st);

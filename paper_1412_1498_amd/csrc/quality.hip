@@ -47,6 +47,57 @@ __device__ __forceinline__ void block_sum2(double &a, double &b) {
     }
 }
 
+// Sums of Re Tr over the functional's forward links and of Tr Delta
+// Delta^dagger at site (p, h), added to fsum / tsum (all in double).
+template <typename R, int NE>
+__device__ __forceinline__ void site_quality(const Geom &g, const gchar *U, int gauge, int p, int h,
+                                             double &fsum, double &tsum) {
+    const int nd = gauge == 0 ? 4 : 3;
+    const SiteNbr nb = site_neighbours(g, p, h);
+    double mr[9], mi[9];
+#pragma unroll
+    for (int e = 0; e < 9; e++) { mr[e] = 0.0; mi[e] = 0.0; }
+    for (int mu = 0; mu < nd; mu++) {
+        Mat<R> f, b;
+        load_link<R, NE, false>(f, U, link_off(g, mu, p, h));
+        load_link<R, NE, false>(b, U, link_off(g, mu, 1 - p, pick4(nb.hb, mu)));
+        fsum += (double)f.re[0] + (double)f.re[4] + (double)f.re[8];
+#pragma unroll
+        for (int e = 0; e < 9; e++) {
+            mr[e] += (double)b.re[e] - (double)f.re[e];
+            mi[e] += (double)b.im[e] - (double)f.im[e];
+        }
+    }
+    // A = M - M^dagger: A_rc = M_rc - conj(M_cr)
+    double ar[9], ai[9];
+#pragma unroll
+    for (int r = 0; r < 3; r++)
+#pragma unroll
+        for (int cc = 0; cc < 3; cc++) {
+            ar[3 * r + cc] = mr[3 * r + cc] - mr[3 * cc + r];
+            ai[3 * r + cc] = mi[3 * r + cc] + mi[3 * cc + r];
+        }
+    const double trr = (ar[0] + ar[4] + ar[8]) / 3.0;
+    const double tri = (ai[0] + ai[4] + ai[8]) / 3.0;
+#pragma unroll
+    for (int r = 0; r < 3; r++) { ar[4 * r] -= trr; ai[4 * r] -= tri; }
+#pragma unroll
+    for (int e = 0; e < 9; e++) tsum += ar[e] * ar[e] + ai[e] * ai[e];
+}
+
+// Partial pair of quality tile `local` of member d (QTILE/2 half indices,
+// both parities), summed over the workgroup: result in lane 0.
+template <typename R, int NE>
+__device__ __forceinline__ void quality_tile(const CfgDesc &d, int local, double &fsum, double &tsum) {
+    constexpr int QH = QTILE / 2;
+    const int p = threadIdx.x >= QH;
+    const int h = local * QH + (int)threadIdx.x - p * QH;
+    fsum = 0.0;
+    tsum = 0.0;
+    if (h < d.g.Vh) site_quality<R, NE>(d.g, as_global(d.U), d.gauge, p, h, fsum, tsum);
+    block_sum2(fsum, tsum);
+}
+
 template <typename R, int NE>
 __global__ void __launch_bounds__(QTILE)
 k_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
@@ -55,57 +106,35 @@ k_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
     const int c = qtile_cfg[tile];
     if (active && !active[c]) return;
     const CfgDesc d = desc[c];
-    const Geom &g = d.g;
-    constexpr int QH = QTILE / 2;
-    const int p = threadIdx.x >= QH;
-    const int h = (tile - d.qtile0) * QH + (int)threadIdx.x - p * QH;
-    const int nd = d.gauge == 0 ? 4 : 3;
-    double fsum = 0.0, tsum = 0.0;
-    if (h < g.Vh) {
-        const SiteNbr nb = site_neighbours(g, p, h);
-        const gchar *U = as_global(d.U);
-        double mr[9], mi[9];
-#pragma unroll
-        for (int e = 0; e < 9; e++) { mr[e] = 0.0; mi[e] = 0.0; }
-        for (int mu = 0; mu < nd; mu++) {
-            Mat<R> f, b;
-            load_link<R, NE, false>(f, U, link_off(g, mu, p, h));
-            load_link<R, NE, false>(b, U, link_off(g, mu, 1 - p, pick4(nb.hb, mu)));
-            fsum += (double)f.re[0] + (double)f.re[4] + (double)f.re[8];
-#pragma unroll
-            for (int e = 0; e < 9; e++) {
-                mr[e] += (double)b.re[e] - (double)f.re[e];
-                mi[e] += (double)b.im[e] - (double)f.im[e];
-            }
-        }
-        // A = M - M^dagger: A_rc = M_rc - conj(M_cr)
-        double ar[9], ai[9];
-#pragma unroll
-        for (int r = 0; r < 3; r++)
-#pragma unroll
-            for (int cc = 0; cc < 3; cc++) {
-                ar[3 * r + cc] = mr[3 * r + cc] - mr[3 * cc + r];
-                ai[3 * r + cc] = mi[3 * r + cc] + mi[3 * cc + r];
-            }
-        const double trr = (ar[0] + ar[4] + ar[8]) / 3.0;
-        const double tri = (ai[0] + ai[4] + ai[8]) / 3.0;
-#pragma unroll
-        for (int r = 0; r < 3; r++) { ar[4 * r] -= trr; ai[4 * r] -= tri; }
-#pragma unroll
-        for (int e = 0; e < 9; e++) tsum += ar[e] * ar[e] + ai[e] * ai[e];
-    }
-    block_sum2(fsum, tsum);
+    double fsum, tsum;
+    quality_tile<R, NE>(d, tile - d.qtile0, fsum, tsum);
     if (threadIdx.x == 0) {
         partials[2 * tile] = fsum;
         partials[2 * tile + 1] = tsum;
     }
 }
 
+constexpr int QFINAL = 1024;
+
+// Sum the nq partial pairs at pp over one workgroup of QFINAL lanes (strided
+// per lane, then the fixed butterfly): result in lane 0.
+__device__ __forceinline__ void sum_partials(const double *__restrict__ partials, int nq, double &fs,
+                                             double &ts) {
+    fs = 0.0;
+    ts = 0.0;
+    const double2 *pp = reinterpret_cast<const double2 *>(partials);
+#pragma unroll 4
+    for (int t = threadIdx.x; t < nq; t += QFINAL) {
+        const double2 v = pp[t];
+        fs += v.x;
+        ts += v.y;
+    }
+    block_sum2(fs, ts);
+}
+
 // One workgroup per member. With update_active: members that were active
 // get iters += swept, and are retired once theta < eps; retired members
 // keep their previous result.
-constexpr int QFINAL = 1024;
-
 __global__ void __launch_bounds__(QFINAL)
 k_quality_final(const CfgDesc *__restrict__ desc, const double *__restrict__ partials,
                 double *__restrict__ result, int *__restrict__ active, int *__restrict__ iters,
@@ -113,15 +142,8 @@ k_quality_final(const CfgDesc *__restrict__ desc, const double *__restrict__ par
     const int c = blockIdx.x;
     if (update_active && !active[c]) return;
     const CfgDesc d = desc[c];
-    double fs = 0.0, ts = 0.0;
-    const double2 *pp = reinterpret_cast<const double2 *>(partials) + d.qtile0;
-#pragma unroll 4
-    for (int t = threadIdx.x; t < d.nqtiles; t += QFINAL) {
-        const double2 v = pp[t];
-        fs += v.x;
-        ts += v.y;
-    }
-    block_sum2(fs, ts);
+    double fs, ts;
+    sum_partials(partials + 2 * (size_t)d.qtile0, d.nqtiles, fs, ts);
     if (threadIdx.x == 0) {
         const int nd = d.gauge == 0 ? 4 : 3;
         const double F = fs / (nd * ncol * (double)d.g.V);
@@ -133,6 +155,65 @@ k_quality_final(const CfgDesc *__restrict__ desc, const double *__restrict__ par
             if (th < eps) active[c] = 0;
         }
     }
+}
+
+// Per time slice t (the Coulomb gauge's diagnostic, also defined for
+// Landau): the same site sums over the nx ny nz sites of slice t, which are
+// the half indices [t st, (t + 1) st) of both parities. Workgroup
+// t * nchunk + chunk takes QTILE/2 of them (both parities) and writes one
+// partial pair; then one workgroup per slice sums its nchunk pairs in the
+// fixed order of the global reduction and normalises by the slice volume.
+template <typename R, int NE>
+__global__ void __launch_bounds__(QTILE)
+k_quality_slices(const CfgDesc d, int nchunk, double *__restrict__ partials) {
+    constexpr int QH = QTILE / 2;
+    const int t = blockIdx.x / nchunk, chunk = blockIdx.x - t * nchunk;
+    const int p = threadIdx.x >= QH;
+    const int k = chunk * QH + (int)threadIdx.x - p * QH;
+    double fsum = 0.0, tsum = 0.0;
+    if (k < d.g.st) site_quality<R, NE>(d.g, as_global(d.U), d.gauge, p, t * d.g.st + k, fsum, tsum);
+    block_sum2(fsum, tsum);
+    if (threadIdx.x == 0) {
+        partials[2 * (size_t)blockIdx.x] = fsum;
+        partials[2 * (size_t)blockIdx.x + 1] = tsum;
+    }
+}
+
+__global__ void __launch_bounds__(QFINAL)
+k_quality_slices_final(const CfgDesc d, int nchunk, const double *__restrict__ partials,
+                       double *__restrict__ out) {
+    const int t = blockIdx.x;
+    double fs, ts;
+    sum_partials(partials + 2 * (size_t)t * nchunk, nchunk, fs, ts);
+    if (threadIdx.x == 0) {
+        const int nd = d.gauge == 0 ? 4 : 3;
+        const double Vt = (double)d.g.nx * d.g.ny * d.g.nz;
+        out[2 * t] = fs / (nd * 3.0 * Vt);
+        out[2 * t + 1] = ts / (3.0 * Vt);
+    }
+}
+
+template <typename R, int NE>
+static hipError_t launch_qs(const CfgDesc &d, int nchunk, double *d_partials, double *d_out, hipStream_t st) {
+    hipLaunchKernelGGL((k_quality_slices<R, NE>), dim3(d.g.nt * nchunk), dim3(QTILE), 0, st, d, nchunk,
+                       d_partials);
+    hipLaunchKernelGGL(k_quality_slices_final, dim3(d.g.nt), dim3(QFINAL), 0, st, d, nchunk, d_partials,
+                       d_out);
+    return hipGetLastError();
+}
+
+int quality_slice_chunks(const Geom &g) { return (g.st + QTILE / 2 - 1) / (QTILE / 2); }
+
+hipError_t launch_quality_slices(int prec, int nelem, const CfgDesc &d, double *d_partials, double *d_out,
+                                 hipStream_t st) {
+    const int nchunk = quality_slice_chunks(d.g);
+#define GF_QS(R)                                                                                  \
+    (nelem == 9   ? launch_qs<R, 9>(d, nchunk, d_partials, d_out, st)                              \
+     : nelem == 6 ? launch_qs<R, 6>(d, nchunk, d_partials, d_out, st)                              \
+                  : launch_qs<R, 4>(d, nchunk, d_partials, d_out, st))
+    const hipError_t e = prec == 0 ? GF_QS(double) : GF_QS(float);
+#undef GF_QS
+    return e;
 }
 
 template <typename R, int NE>

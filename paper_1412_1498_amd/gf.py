@@ -47,6 +47,7 @@ class Params(ctypes.Structure):
         ("nontemporal", ctypes.c_int),
         ("use_graph", ctypes.c_int),
         ("timing", ctypes.c_int),
+        ("log_path", ctypes.c_char_p),
     ]
 
 
@@ -62,6 +63,8 @@ def _load():
         "gf_create": (I, [PP, P, I, I, I, P, ctypes.POINTER(Params)]),
         "gf_batch_create": (I, [PP, I, P, P, I, P, ctypes.POINTER(Params)]),
         "gf_destroy": (I, [P]),
+        "gf_batch_destroy": (I, [P]),
+        "gf_quality_slices": (I, [P, P, P, P]),
         "gf_last_error": (ctypes.c_char_p, [P]),
         "gf_field_bytes": (ctypes.c_size_t, [P, I]),
         "gf_pack": (I, [P, P, P]),
@@ -106,7 +109,10 @@ def default_params(prec=F32, **kw) -> Params:
     for k, v in kw.items():
         if not hasattr(p, k):
             raise TypeError(f"unknown gf_params field {k}")
-        setattr(p, k, int(v))
+        if k == "log_path":
+            p.log_path = None if v is None else os.fsencode(v)
+        else:
+            setattr(p, k, int(v))
     return p
 
 
@@ -167,7 +173,7 @@ class Context:
     # -- lifetime -------------------------------------------------------------
     def close(self):
         if self._h:
-            lib.gf_destroy(self._h)
+            (lib.gf_batch_destroy if self.n > 1 else lib.gf_destroy)(self._h)
             self._h = ctypes.c_void_p()
 
     def __del__(self):
@@ -256,6 +262,13 @@ class Context:
         self._check(lib.gf_quality(self._h, ctypes.c_void_p(self._check_field(U)),
                                    ctypes.byref(F), ctypes.byref(th)))
         return F.value, th.value
+
+    def quality_slices(self, U):
+        """(F_t, theta_t) per time slice t of member 0, as lists of nt floats."""
+        nt = self.members[0][0][3]
+        Ft, tht = (ctypes.c_double * nt)(), (ctypes.c_double * nt)()
+        self._check(lib.gf_quality_slices(self._h, ctypes.c_void_p(self._check_field(U)), Ft, tht))
+        return list(Ft), list(tht)
 
     def fix(self, U, omega, eps, max_iter):
         it, F, th = ctypes.c_int(), ctypes.c_double(), ctypes.c_double()
