@@ -136,6 +136,7 @@ def run_ensemble(args, gf, synth, torch, np):
     out["sequential_fp64"] = dict(seconds=t64)
     out["batched_speedup_vs_sequential_fp32"] = t32 / tb
     out["batched_speedup_vs_sequential_fp64"] = t64 / tb
+    out["batched_over_fp64"] = t64 / tb
     out["max_abs_F_fp32_batched_minus_fp64"] = max(abs(a - b) for a, b in zip(rb["F"], F64))
     return out
 
@@ -285,6 +286,97 @@ def run_sd(args, dims, gf, synth, torch):
     return res
 
 
+def run_precision_32(gf, synth, torch):
+    """Precision line at 32^4 (Landau, amp 0.5, seed 0, omega 1.7, checks and
+    reunitarisation every 10 sweeps): the plain FP64 GPU form to theta < 1e-12
+    and to theta < 1e-7, and FP32 links (FP64 sums, solve, reunitarisation and
+    F/theta) to theta < 1e-7; wall time of each gf_fix."""
+    dims = (32, 32, 32, 32)
+    U64 = synth.random_gauge_field(dims, 0.5, 0, device="cuda")
+    res = {"workload": "SU(3) Landau, 32x32x32x32, amp 0.5, seed 0, omega 1.7, check and reunit every 10 sweeps"}
+    for name, prec, eps in (("fp64_to_1e-12", gf.F64, 1e-12), ("fp64_to_1e-7", gf.F64, 1e-7),
+                            ("fp32_to_1e-7", gf.F32, 1e-7)):
+        log(f"32^4 {name}")
+        ctx = gf.Context(dims, gauge=gf.LANDAU, prec=prec,
+                         params=gf.default_params(prec, check_every=10, reunit_every=10))
+        U = ctx.pack(U64 if prec == gf.F64 else U64.to(torch.complex64))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.fix(U, 1.7, eps, 20000)
+        torch.cuda.synchronize()
+        res[name] = dict(seconds=time.perf_counter() - t0, sweeps=r["iters"], converged=r["converged"],
+                         F=r["F"], theta=r["theta"])
+        del U, ctx
+        torch.cuda.empty_cache()
+    res["fp32_speedup_to_theta_1e-7"] = res["fp64_to_1e-7"]["seconds"] / res["fp32_to_1e-7"]["seconds"]
+    res["abs_F_fp32_minus_fp64_1e-12"] = abs(res["fp32_to_1e-7"]["F"] - res["fp64_to_1e-12"]["F"])
+    return res, U64
+
+
+def run_cpu_baseline(gf, synth, torch, fields, main_name, gpu_value, gpu_fp64_time_16):
+    """The FP64 C oracle on the host cores: site-sweeps/s over whole sweeps
+    (even + odd half-sweep) of the benchmark's own fields, with one thread
+    and with the threads of this process's CPU share (at most 16); and the
+    time to theta < 1e-12 at 4^4 and 16^4 (amp 0.3, seed 0, omega 1.7,
+    reunitarisation every 20 sweeps) next to the FP64 GPU time."""
+    import oracle
+    share = min(16, len(os.sched_getaffinity(0)))
+    before = oracle.set_threads(0)
+    runs = []
+    plan = [(1, "32x32x32x32", 3), (share, "32x32x32x32", 5), (share, main_name, 5)]
+    for threads, name, nsw in plan:
+        Uh, dims = fields[name]
+        A = Uh.copy()
+        oracle.set_threads(threads)
+        log(f"CPU oracle: {nsw} FP64 sweeps at {name} on {threads} thread(s)")
+        t0 = time.perf_counter()
+        for _ in range(nsw):
+            oracle.sweep(A, dims, 1.7)
+        dt = time.perf_counter() - t0
+        V = dims[0] * dims[1] * dims[2] * dims[3]
+        runs.append(dict(threads=threads, lattice=name, sweeps=nsw, seconds=dt, site_sweeps_per_s=V * nsw / dt))
+        del A
+    conv = {}
+    oracle.set_threads(share)
+    for L in (4, 16):
+        dims = (L, L, L, L)
+        Uh = synth.random_gauge_field(dims, 0.3, 0).numpy()
+        log(f"CPU oracle: {L}^4 to theta < 1e-12 on {share} threads")
+        t0 = time.perf_counter()
+        ro = oracle.fix(Uh, dims, 1.7, 1e-12, 20000, reunit_every=20)
+        conv[f"{L}x4"] = dict(threads=share, seconds=time.perf_counter() - t0, sweeps=ro["iters"],
+                              converged=ro["converged"], theta=ro["theta"])
+    conv["16x4"]["gpu_fp64_seconds"] = gpu_fp64_time_16
+    oracle.set_threads(before)
+    main = runs[2]
+    return {
+        "value": main["site_sweeps_per_s"],
+        "unit": "site-sweeps/s",
+        "cores": share,
+        "kind": "oracle",
+        "sample": f"5 FP64 sweeps (even + odd half-sweep) of the benchmark's {main_name} field by the C oracle "
+                  f"on {share} threads ({main['seconds']:.1f} s); also 1 thread at 32^4 and runs to "
+                  f"theta < 1e-12 at 4^4 and 16^4",
+        "runs": runs,
+        "to_theta_1e-12": conv,
+        "gpu_over_cpu_threads": gpu_value / main["site_sweeps_per_s"],
+        "gpu_over_cpu_1_thread": gpu_value / runs[0]["site_sweeps_per_s"],
+    }
+
+
+def gpu_fp64_time_16(gf, synth, torch):
+    """FP64 GPU time to theta < 1e-12 at 16^4 (amp 0.3, seed 0, omega 1.7,
+    reunitarisation every 20 sweeps, check every sweep), as the oracle runs it."""
+    dims = (16, 16, 16, 16)
+    ctx = gf.Context(dims, gauge=gf.LANDAU, prec=gf.F64, params=gf.default_params(gf.F64, reunit_every=20))
+    U = ctx.pack(synth.random_gauge_field(dims, 0.3, 0, device="cuda"))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = ctx.fix(U, 1.7, 1e-12, 20000)
+    torch.cuda.synchronize()
+    return dict(seconds=time.perf_counter() - t0, sweeps=r["iters"], converged=r["converged"])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -304,6 +396,10 @@ def main():
     ap.add_argument("--no-8real", action="store_true", help="skip the 8-real FP32 storage leg")
     ap.add_argument("--no-convergence", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-precision-32", action="store_true",
+                    help="skip the 32^4 FP64 / FP32 runs to theta < 1e-12 / 1e-7")
+    ap.add_argument("--no-ensemble", action="store_true",
+                    help="skip the ensemble leg (Coulomb 48^3x96 + 64 uneven Landau lattices)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation timing leg")
     ap.add_argument("--no-sun", action="store_true", help="skip the SU(2) / SU(4) leg")
     ap.add_argument("--no-bw-reference", action="store_true",
@@ -560,24 +656,26 @@ def main():
         torch.cuda.synchronize()
         out["copy_probe_bytes"] = 2 * a.numel() * 4
 
+    U32f = None
+    if not args.no_precision_32:
+        out["precision_32x4"], U32f = run_precision_32(gf, synth, torch)
+
+    if not args.no_ensemble:
+        ens = run_ensemble(args, gf, synth, torch, np)
+        ens.pop("workload", None)
+        out["ensemble"] = ens
+
     if not args.no_cpu_baseline:
-        import oracle
-        log("CPU oracle: one full FP64 sweep of the same field on the host")
-        Uh = U64.cpu().numpy()
+        fields = {"x".join(map(str, dims)): (U64.cpu().numpy(), dims)}
         del U64
+        if U32f is None:
+            U32f = synth.random_gauge_field((32, 32, 32, 32), 0.5, 0, device="cuda")
+        fields["32x32x32x32"] = (U32f.cpu().numpy(), (32, 32, 32, 32))
+        del U32f
         torch.cuda.empty_cache()
-        t0 = time.perf_counter()
-        oracle.sweep(Uh, dims, args.omega)
-        dt = time.perf_counter() - t0
-        out["cpu_baseline"] = {
-            "value": V / dt,
-            "unit": "site-sweeps/s",
-            "cores": 1,
-            "kind": "oracle",
-            "sample": f"one full sweep (even + odd half-sweep) of the same {'x'.join(map(str, dims))} field "
-                      f"in FP64 by the single-threaded C oracle, {dt:.1f} s",
-        }
-        out["gpu_over_cpu"] = value / out["cpu_baseline"]["value"]
+        t16 = gpu_fp64_time_16(gf, synth, torch)
+        out["cpu_baseline"] = run_cpu_baseline(gf, synth, torch, fields, "x".join(map(str, dims)), value, t16)
+        out["gpu_over_cpu"] = out["cpu_baseline"]["gpu_over_cpu_threads"]
 
     print(json.dumps(out), flush=True)
 
