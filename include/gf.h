@@ -46,13 +46,15 @@
  *   e = 0, 1, 2 hold U01, U02, U10 and e = 3 holds the pair (phase code of
  *   U00, phase code of U20), where the code of z with w = z/|z| is
  *   t = Im w / (1 + |Re w|) if Re w >= 0, else 2 - t (t >= 0) or -2 - t
- *   (t < 0), and 0 for z = 0; the rest follows from unitarity and det U = 1:
+ *   (t < 0), and 4 for z = 0; the rest follows from unitarity and det U = 1:
  *   |U00|^2 = 1 - n2, |U20|^2 = n2 - |U10|^2 with n2 = |U01|^2 + |U02|^2,
  *   U11 = -(conj(U00) U01 U10 + conj(U02) conj(U20)) / n2,
  *   U12 = (conj(U01) conj(U20) - conj(U00) U02 U10) / n2,
- *   U21 = -conj(U00 U12 - U02 U10), U22 = conj(U00 U11 - U01 U10); a link
- *   with U01 = U02 = 0 exactly cannot be held and reads back as
- *   diag(U00, conj(U00), 1)). The last block of a parity is padded.
+ *   U21 = -conj(U00 U12 - U02 U10), U22 = conj(U00 U11 - U01 U10); for a
+ *   link with U01 = U02 = 0 exactly (then U10 = U20 = 0) e = 2 holds U11
+ *   and the second code is that of U12, |U12|^2 = 1 - |U11|^2,
+ *   U21 = -conj(U00 U12), U22 = conj(U00 U11)). The last block of a parity
+ *   is padded.
  * - SU(N): a single-lattice context may also hold N = 2 or 4 colours (the
  *   paper's method for general N: all N(N-1)/2 SU(2) subgroups (a, b), a < b,
  *   in lexicographic order). Its links are full N x N matrices in the same

@@ -179,3 +179,71 @@ def test_full_size_48_fp32_sampled_sites(gf, oracle_lib):
             idx.append((s - step if c > 0 else s + 47 * step, mu))
         for i, mu in idx:
             check(back[i, mu], O[i, mu], 1, 5e-6)
+
+
+@pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
+@pytest.mark.parametrize("amp", [0.3, 0.0])
+def test_fp64_fix_to_1e12_matches_oracle(gf, oracle_lib, field_cache, gauge, amp):
+    """Alg. 1 in FP64 on 8-real links to theta < 1e-12 (4^4, seed 0; amp 0.3
+    as the small FP64 case, and amp 0, a pure gauge whose fixed links are
+    the unit matrix, where the format's u/eps behaviour near 1 shows): the
+    run converges and lands on the oracle's F and field, the oracle started
+    from the GPU's reconstructed field."""
+    dims = (4, 4, 4, 4)
+    U = field_cache(dims, amp, 0)
+    ctx = make_ctx(gf, dims, gauge, 0, reunit_every=20)
+    Ug = to_gpu(ctx, U)
+    Uo = to_host(ctx, Ug)
+    r = ctx.fix(Ug, 1.7, 1e-12, 2000)
+    ro = oracle_lib.fix(Uo, dims, 1.7, 1e-12, 2000, gauge, reunit_every=20)
+    got = to_host(ctx, Ug)
+    err = np.abs(got - Uo).max()
+    print(f"amp {amp} gauge {gauge}: iters {r['iters']} (oracle {ro['iters']}), theta {r['theta']:.2e}, "
+          f"|dF| {abs(r['F'] - ro['F']):.1e}, max|dU| {err:.1e}")
+    assert r["converged"] and ro["converged"] and r["theta"] < 1e-12
+    assert r["iters"] == ro["iters"]
+    assert abs(r["F"] - ro["F"]) < 1e-12
+    assert err < 1e-12  # measured 8e-14 .. 1.2e-13
+    if amp == 0.0:
+        assert abs(r["F"] - 1) < 1e-12
+
+
+def degenerate_links(rng, n):
+    """n SU(3) links with U01 = U02 = 0: diag(a) and a U(2) block of
+    determinant conj(a) (a few exactly diagonal ones among them)."""
+    out = np.zeros((n, 3, 3), dtype=np.complex128)
+    for k in range(n):
+        a = np.exp(1j * rng.uniform(-np.pi, np.pi))
+        z = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        if k % 7 == 0:
+            z[1] = 0
+        z /= np.linalg.norm(z)
+        out[k, 0, 0] = a
+        out[k, 1:, 1:] = [[z[0], z[1]], [-np.conj(a * z[1]), np.conj(a * z[0])]]
+    return out
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_links_without_off_diagonal_row0(gf, oracle_lib, prec):
+    """Every link with U01 = U02 = 0 exactly: the field packs and unpacks to
+    itself (U11 and the phase of U12 take the free slots), and half-sweeps
+    from it follow the oracle."""
+    dims = (4, 4, 2, 2)
+    V = int(np.prod(dims))
+    U = degenerate_links(np.random.default_rng(8), 4 * V).reshape(dims[3], dims[2], dims[1], dims[0], 4, 3, 3)
+    ctx = make_ctx(gf, dims, LANDAU, prec)
+    Ug = to_gpu(ctx, U)
+    back = to_host(ctx, Ug)
+    src = U.astype(np.complex64).astype(np.complex128) if prec == 1 else U
+    u = U32 if prec == 1 else U64
+    b = np.abs(src[..., 1, 2])
+    with np.errstate(divide="ignore"):
+        bound = 8 * u * (1 + np.where(b > 0, 1 / b, 0))
+    assert (np.abs(back - src).max(axis=(-1, -2)) <= bound).all()
+    assert (back[..., 0, 1] == 0).all() and (back[..., 1, 0] == 0).all()
+    base = 1e-13 if prec == 0 else 5e-6
+    for p in (0, 1):
+        cur = to_host(ctx, Ug)
+        ctx.sweep(Ug, p, 1.7)
+        oracle_lib.half_sweep(cur, dims, p, 1.7)
+        check(to_host(ctx, Ug), cur, prec, base)

@@ -28,7 +28,10 @@ def haar(rng):
 
 def decode_phase(p):
     """The unit complex number of a stored phase code (the format's
-    definition: t = Im w / (1 + |Re w|), shifted by 2 when Re w < 0)."""
+    definition: t = Im w / (1 + |Re w|), shifted by 2 when Re w < 0; 4 codes
+    the number 0)."""
+    if abs(p) > 3:
+        return 0j
     neg = abs(p) > 1
     t = np.copysign(2 - abs(p), p) if neg else p
     c = (1 - t * t) / (1 + t * t)
@@ -102,14 +105,41 @@ def test_fp64_round_trip_near_the_unit_matrix(gf):
 
 @pytest.mark.parametrize("prec", [0, 1])
 def test_links_without_off_diagonal_row0(gf, prec):
-    """U01 = U02 = 0 exactly: the lower 2x2 block is not stored and reads back
-    as diag(conj U00, 1), which is right for diag(a, conj a, 1) only."""
-    a = cmath.exp(0.3j)
-    D = np.diag([a, a.conjugate(), 1.0])
-    _, out = gf.host_link8(prec, D)
-    assert abs(out - D).max() < 4 * (U32 if prec == 1 else U64)
-    _, out = gf.host_link8(prec, np.diag([1j, 1j, -1.0]))
-    assert abs(out - np.diag([1j, -1j, 1.0])).max() < 4 * (U32 if prec == 1 else U64)
+    """U01 = U02 = 0 exactly (the unit matrix, diagonal links, diag(a) + a
+    U(2) block of determinant conj(a)): U10 = U20 = 0 follow from unitarity,
+    and the stored reals hold U11 and the phase of U12 instead; every such
+    link comes back to within a few units of roundoff, and its stored reals
+    are the documented ones."""
+    u = U32 if prec == 1 else U64
+    rng = np.random.default_rng(7)
+    cases = [np.eye(3, dtype=complex), np.diag([1j, 1j, -1.0]), np.diag([-1.0, -1.0, 1.0]),
+             np.diag([1.0, -1.0, -1.0])]
+    for ang in (0.3, -2.0, np.pi):
+        a = cmath.exp(1j * ang)
+        cases.append(np.diag([a, a.conjugate(), 1.0]))
+        b = cmath.exp(0.7j)
+        cases.append(np.diag([a, b, (a * b).conjugate()]))
+    for _ in range(200):
+        a = cmath.exp(1j * rng.uniform(-np.pi, np.pi))
+        z = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        z /= np.linalg.norm(z)
+        B = np.array([[z[0], z[1]], [-a.conjugate() * z[1].conjugate(), a.conjugate() * z[0].conjugate()]])
+        U = np.zeros((3, 3), dtype=complex)
+        U[0, 0] = a
+        U[1:, 1:] = B
+        cases.append(U)
+    for U in cases:
+        assert abs(np.linalg.det(U) - 1) < 1e-14 and abs(U @ U.conj().T - np.eye(3)).max() < 1e-14
+        Ui = U.astype(np.complex64).astype(np.complex128) if prec == 1 else U
+        st, out = gf.host_link8(prec, U)
+        assert st[0] == st[1] == st[2] == st[3] == 0
+        assert st[4] + 1j * st[5] == Ui[1, 1]
+        b = abs(Ui[1, 2])
+        assert abs(decode_phase(st[7]) - (Ui[1, 2] / b if b > 0 else 0)) < 8 * u
+        # |U12| = sqrt(1 - |U11|^2) loses digits when it is small, as |U20| does
+        assert abs(out - Ui).max() < 8 * u * (1 + (1 / b if b > 0 else 0)), (U, out)
+        if b == 0:
+            assert out[1, 2] == 0 and out[2, 1] == 0
     # the phase code on the axes and on both sides of the branch at -1
     for ang in (0.0, np.pi / 2, -np.pi / 2, np.pi, np.pi - 1e-6, -np.pi + 1e-6, np.pi / 2 + 1e-6,
                 np.pi / 2 - 1e-6):
