@@ -157,7 +157,9 @@ int gf_batch_create(gf_ctx **out, int n, const int *dims, const int *gauge, int 
 int gf_destroy(gf_ctx *ctx);
 int gf_batch_destroy(gf_ctx *ctx);
 
-/* Human-readable description of the last error on ctx ("" if none). */
+/* Human-readable description of the last error on ctx ("" if none); with
+ * ctx = NULL, that of the last failed context-free call (gf_quality_noalloc)
+ * on the calling thread. */
 const char *gf_last_error(const gf_ctx *ctx);
 
 /* Bytes of one field of member i in the internal layout:
@@ -201,6 +203,26 @@ int gf_quality(gf_ctx *ctx, const void *U, double *F, double *theta);
  * 2 nt ceil(nx ny nz / 256) + 2 nt doubles of scratch (kept by the context).
  * Synchronises. GF_ENONFINITE if a value is NaN or Inf. */
 int gf_quality_slices(gf_ctx *ctx, const void *U, double *F_t, double *theta_t);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): F and
+ * theta of gf_quality for one SU(3) lattice without a context and without
+ * any allocation. U is a field of the given dims, gauge, precision and
+ * storage (GF_STORE_*) in the internal layout; out is a caller-owned DEVICE
+ * array of 2 doubles receiving {F, theta}, bitwise those gf_quality returns
+ * for the same field. Runs on the current device, asynchronously on stream
+ * (a hipStream_t of that device; NULL = default stream), with no host
+ * synchronisation and no allocating call (hipMalloc, hipFree, pinned
+ * memory), so it may be captured into a graph. Its reduction scratch is a
+ * fixed device array of the library (1 MiB per GPU, held until the process
+ * ends), which limits the lattice to V <= 2^24 sites (65536 tiles of 256
+ * sites; 48^3 x 96 fits): larger lattices return GF_EINVAL before any
+ * device work, as do bad dims, gauge, precision, storage or pointers;
+ * gf_last_error(NULL) then says why. All calls on one GPU share that array:
+ * calls that may overlap in time on one GPU (several streams or threads)
+ * race on it and must be ordered by the caller. */
+int gf_quality_noalloc(const void *U, const int dims[4], int gauge, int prec, int storage, void *stream,
+                       double *out);
 
 /* Alg. 1 on member 0: compute F, theta; while theta >= eps and fewer than
  * max_iter sweeps were done: sweep (with scheduled reunitarisation) and

@@ -19,7 +19,7 @@ OUT = os.path.join(HERE, "libgf.so")
 BUILD = os.path.join(ROOT, "_build")
 ARCH = os.environ.get("GF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "sweep.hip", "quality.hip", "layout.hip", "grad.hip", "fft.hip", "sun.hip"]
+SOURCES = ["api.cpp", "sweep.hip", "quality.hip", "layout.hip", "grad.hip", "fft.hip", "sun.hip", "noalloc.hip"]
 
 CFLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

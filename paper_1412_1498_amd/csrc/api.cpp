@@ -473,7 +473,7 @@ int gf_destroy(gf_ctx *ctx) {
 
 int gf_batch_destroy(gf_ctx *ctx) { return gf_destroy(ctx); }
 
-const char *gf_last_error(const gf_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char *gf_last_error(const gf_ctx *ctx) { return ctx ? ctx->err.c_str() : noalloc_last_error(); }
 
 size_t gf_field_bytes(const gf_ctx *ctx, int member) {
     if (!ctx || member < 0 || member >= ctx->n) return 0;

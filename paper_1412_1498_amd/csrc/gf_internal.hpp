@@ -133,6 +133,12 @@ hipError_t launch_quality_final(const CfgDesc *d_desc, int n, const double *d_pa
 int quality_slice_chunks(const Geom &g);
 hipError_t launch_quality_slices(int prec, int nelem, const CfgDesc &d, double *d_partials, double *d_out,
                                  hipStream_t st);
+// F and theta of one lattice given by value (d.qtile0 = 0, d.nqtiles tiles):
+// d_partials holds 2 * d.nqtiles doubles, d_out receives {F, theta}.
+hipError_t launch_quality_one(int prec, int nelem, const CfgDesc &d, double *d_partials, double *d_out,
+                              hipStream_t st);
+// Message of the last failed context-free call on this thread.
+const char *noalloc_last_error();
 hipError_t launch_pack(int prec, int nelem, const Geom &g, const void *aos, void *U, int unpack,
                        hipStream_t st);
 hipError_t launch_reunit(int prec, int nelem, const Geom &g, void *U, hipStream_t st);

@@ -216,6 +216,51 @@ hipError_t launch_quality_slices(int prec, int nelem, const CfgDesc &d, double *
     return e;
 }
 
+// One member given by value (no member table, no tile map): the tiles,
+// their order and the final reduction of k_quality / k_quality_final for a
+// single lattice, so the results are bitwise those of the context path.
+template <typename R, int NE>
+__global__ void __launch_bounds__(QTILE)
+k_quality_one(const CfgDesc d, double *__restrict__ partials) {
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    double fsum, tsum;
+    quality_tile<R, NE>(d, tile, fsum, tsum);
+    if (threadIdx.x == 0) {
+        partials[2 * tile] = fsum;
+        partials[2 * tile + 1] = tsum;
+    }
+}
+
+__global__ void __launch_bounds__(QFINAL)
+k_quality_one_final(const CfgDesc d, const double *__restrict__ partials, double *__restrict__ out) {
+    double fs, ts;
+    sum_partials(partials, d.nqtiles, fs, ts);
+    if (threadIdx.x == 0) {
+        const int nd = d.gauge == 0 ? 4 : 3;
+        const double ncol = 3.0;
+        out[0] = fs / (nd * ncol * (double)d.g.V);
+        out[1] = ts / (ncol * (double)d.g.V);
+    }
+}
+
+template <typename R, int NE>
+static hipError_t launch_q1(const CfgDesc &d, double *d_partials, double *d_out, hipStream_t st) {
+    hipLaunchKernelGGL((k_quality_one<R, NE>), dim3(d.nqtiles), dim3(QTILE), 0, st, d, d_partials);
+    hipLaunchKernelGGL(k_quality_one_final, dim3(1), dim3(QFINAL), 0, st, d, d_partials, d_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_quality_one(int prec, int nelem, const CfgDesc &d, double *d_partials, double *d_out,
+                              hipStream_t st) {
+#define GF_Q1(R)                                                                                  \
+    (nelem == 9   ? launch_q1<R, 9>(d, d_partials, d_out, st)                                      \
+     : nelem == 6 ? launch_q1<R, 6>(d, d_partials, d_out, st)                                      \
+                  : launch_q1<R, 4>(d, d_partials, d_out, st))
+    const hipError_t e = prec == 0 ? GF_Q1(double) : GF_Q1(float);
+#undef GF_Q1
+    return e;
+}
+
 template <typename R, int NE>
 static hipError_t launch_q(const CfgDesc *d_desc, const int *d_qtile_cfg, const int *d_active,
                            int nqtiles, double *d_partials, hipStream_t st) {

@@ -65,6 +65,7 @@ def _load():
         "gf_destroy": (I, [P]),
         "gf_batch_destroy": (I, [P]),
         "gf_quality_slices": (I, [P, P, P, P]),
+        "gf_quality_noalloc": (I, [P, P, I, I, I, P, P]),
         "gf_last_error": (ctypes.c_char_p, [P]),
         "gf_field_bytes": (ctypes.c_size_t, [P, I]),
         "gf_pack": (I, [P, P, P]),
