@@ -214,12 +214,19 @@ __device__ __forceinline__ void or_site(const CfgDesc &d, int p, int h, int sub)
     }
 }
 
+// Waves per SIMD the compiler is asked to leave room for in the float
+// 8-real sweep (decoding and encoding make its compute phase the longest of
+// the storage forms); every other form fits one wave's registers.
+#ifndef GF_SWEEP8_WAVES
+#define GF_SWEEP8_WAVES 2
+#endif
+
 // One workgroup per tile of blockDim/LPS sites of one member. (A persistent
 // grid-stride form was measured to double the register footprint, since
 // loop-invariant state stays live across the tile loop, so every tile gets
 // its own workgroup; the dispatcher balances the tiles over the CUs.)
 template <typename R, int NE, int LPS, bool NT, bool RU>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NE == 4 && sizeof(R) == 4) ? 2 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NE == 4 && sizeof(R) == 4) ? GF_SWEEP8_WAVES : 1)))
 k_half_sweep(const CfgDesc *__restrict__ desc, const int *__restrict__ tile_cfg,
              const int *__restrict__ active, int parity) {
     const int tile = blockIdx.x;

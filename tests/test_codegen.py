@@ -43,6 +43,7 @@ def kernel_meta(asm):
             "lds": int(re.search(r"\.group_segment_fixed_size:\s+(\d+)", block).group(1)),
             "scratch": int(re.search(r"\.private_segment_fixed_size:\s+(\d+)", block).group(1)),
             "vgpr_spill": int(re.search(r"\.vgpr_spill_count:\s+(\d+)", block).group(1)),
+            "vgpr": int(re.search(r"\.vgpr_count:\s+(\d+)", block).group(1)),
         }
     return meta
 
@@ -65,6 +66,18 @@ def test_sweep_kernels_keep_links_in_registers(tmp_path):
         # registers by design; every other form fits
         if "IfLi4E" not in name:
             assert m["scratch"] == 0 and m["vgpr_spill"] == 0, (name, m)
+
+
+def test_float_8real_sweep_runs_two_waves_per_simd(tmp_path):
+    """The float 8-real sweep was timed at 48^4 for lanes per site 1 and 2
+    and one or two waves per SIMD: 373 us per half-sweep (LPS 1, two waves),
+    418 us (LPS 2, either), 510 us (LPS 1, one wave). The fastest needs at
+    most 256 VGPRs, which it gets for a spill of a few registers."""
+    meta = kernel_meta(device_asm("sweep.hip", tmp_path))
+    f8 = {k: v for k, v in meta.items() if "k_half_sweep" in k and "IfLi4E" in k}
+    assert len(f8) >= 12
+    for name, m in f8.items():
+        assert m["vgpr"] <= 256 and m["vgpr_spill"] <= 12 and m["lds"] == 0, (name, m)
 
 
 def test_sun_sweep_kernels_keep_links_in_registers(tmp_path):
