@@ -218,41 +218,55 @@ def bw_reference(torch, nbytes, achieved_gbs):
     return res
 
 
-def run_diff(gf, synth, torch):
-    """Differentiation line: F_U[g] and its hand-written backward at 24^4
-    (amp 0.4, s_a ~ N(0, 0.1^2)), FP32 and FP64; 20 timed calls each."""
-    ddims = (24, 24, 24, 24)
-    Vd = 24 ** 4
-    Ud = synth.random_gauge_field(ddims, 0.4, 0, device="cuda")
-    sd = synth.random_algebra_field(ddims, 0.1, 1)
-    diffres = {}
-    for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
-        ctx = gf.Context(ddims, gauge=gf.LANDAU, prec=prec)
-        U = ctx.pack(Ud.to(ctx.cdtype))
-        s = ctx.pack_alg(sd.to("cuda", dtype=ctx.rdtype))
-        grad = ctx.functional_grad(U, s)
-        ctx.functional(U, s)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(20):
-            ctx.functional(U, s)
-        tf = (time.perf_counter() - t0) / 20
-        t0 = time.perf_counter()
-        for _ in range(20):
-            ctx.functional_grad(U, s, 1.0, out=grad)
-        torch.cuda.synchronize()
-        tb = (time.perf_counter() - t0) / 20
-        t0 = time.perf_counter()
-        for _ in range(20):
-            ctx.gauge_transform(U, s)
-        torch.cuda.synchronize()
-        tg = (time.perf_counter() - t0) / 20
-        diffres[name] = dict(forward_ms=tf * 1e3, backward_ms=tb * 1e3, gauge_transform_ms=tg * 1e3,
-                             sites_per_s_backward=Vd / tb)
-        del U, s, grad, ctx
-    del Ud
-    torch.cuda.empty_cache()
-    return diffres
+def run_diff(gf, synth, torch, sizes=(24, 48)):
+    """Differentiation line: F_U[g] (gf_functional), its hand-written
+    backward (gf_functional_grad) and the gauge transformation at L^4 for
+    each L in sizes (amp 0.4, s_a ~ N(0, 0.1^2)), FP32 and FP64; 3 warm-up
+    and 20 timed calls each, HIP events on the context's stream. Each call
+    runs two kernels: g = exp(S(s)) into the g field, then the call's own.
+    Algorithmic bytes per site (each datum once; r = bytes of a real): the
+    exponential reads s (8r) and writes g (18r); the functional reads the
+    four forward links (72r) and g (18r); the gradient reads all four links
+    (72r), g (18r) and s (8r) and writes the gradient (8r); the
+    transformation reads and writes the links (144r) and reads g (18r)."""
+    res = {}
+    for L in sizes:
+        ddims = (L, L, L, L)
+        Vd = L ** 4
+        Ud = synth.random_gauge_field(ddims, 0.4, 0, device="cuda")
+        sd = synth.random_algebra_field(ddims, 0.1, 1)
+        out = {}
+        for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
+            r = 4 if prec == gf.F32 else 8
+            bytes_site = {"forward": (26 + 90) * r, "backward": (26 + 106) * r, "gauge_transform": (26 + 162) * r}
+            ctx = gf.Context(ddims, gauge=gf.LANDAU, prec=prec)
+            U = ctx.pack(Ud.to(ctx.cdtype))
+            s = ctx.pack_alg(sd.to("cuda", dtype=ctx.rdtype))
+            grad = ctx.functional_grad(U, s)
+            calls = {"forward": lambda: ctx.functional(U, s),
+                     "backward": lambda: ctx.functional_grad(U, s, 1.0, out=grad),
+                     "gauge_transform": lambda: ctx.gauge_transform(U, s)}
+            entry = {}
+            for what, fn in calls.items():
+                for _ in range(3):
+                    fn()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(20):
+                    fn()
+                e1.record()
+                e1.synchronize()
+                sec = e0.elapsed_time(e1) / 20 / 1e3
+                gbs = bytes_site[what] * Vd / sec / 1e9
+                entry[what] = dict(ms=sec * 1e3, algorithmic_bytes_per_site=bytes_site[what], achieved_gbs=gbs,
+                                   frac=gbs / PEAK_HBM_GBS)
+            entry["sites_per_s_backward"] = Vd / (entry["backward"]["ms"] / 1e3)
+            out[name] = entry
+            del U, s, grad, ctx
+        res[f"{L}x4"] = out
+        del Ud
+        torch.cuda.empty_cache()
+    return res
 
 
 def run_sd(args, dims, gf, synth, torch):
@@ -432,8 +446,13 @@ def main():
                           "sun": run_sun(args, dims, gf, synth, torch)}), flush=True)
         return
     if args.workload == "diff":
-        print(json.dumps({"workload": "differentiation: F_U[g], its gradient and the gauge transformation, 24^4",
-                          "differentiation_24x4": run_diff(gf, synth, torch)}), flush=True)
+        out = {"workload": "differentiation: F_U[g], its gradient and the gauge transformation, 24^4 and 48^4",
+               "differentiation": run_diff(gf, synth, torch)}
+        if args.copy_probe:
+            a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+            torch.empty_like(a).copy_(a)
+            torch.cuda.synchronize()
+        print(json.dumps(out), flush=True)
         return
     if args.workload == "sd":
         out = {"workload": "steepest descent with Fourier acceleration (Alg. 2), Landau gauge, alpha 0.08",
@@ -640,7 +659,7 @@ def main():
         out["convergence"] = conv
 
     if not args.no_diff:
-        out["differentiation_24x4"] = run_diff(gf, synth, torch)
+        out["differentiation"] = run_diff(gf, synth, torch)
 
     if not args.no_sun:
         out["sun"] = run_sun(args, dims, gf, synth, torch)

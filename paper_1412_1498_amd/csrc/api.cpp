@@ -49,6 +49,7 @@ struct gf_ctx {
     int ntiles = 0;
     int *d_qtile_cfg = nullptr;
     int nqtiles = 0;
+    SlabOrder qslab{0, 0, 0};        // quality tile order (single lattices only)
     double *d_partials = nullptr;
     double *d_result = nullptr;      // 2 per member
     int *d_active = nullptr;         // per member (batch driver)
@@ -297,10 +298,10 @@ int full_sweeps(gf_ctx *ctx, int n, const int *d_active, hipStream_t st) {
 int quality_launch(gf_ctx *ctx, const int *d_active, int update, int swept, double eps, hipStream_t st) {
     if (ctx->nc == 3)
         HIPTRY(ctx, launch_quality(ctx->prec, ctx->nelem, ctx->d_desc, ctx->d_qtile_cfg, d_active,
-                                   ctx->nqtiles, ctx->d_partials, st));
+                                   ctx->nqtiles, ctx->d_partials, ctx->qslab, st));
     else
         HIPTRY(ctx, launch_sun_quality(ctx->prec, ctx->nc, ctx->d_desc, ctx->d_qtile_cfg, d_active,
-                                       ctx->nqtiles, ctx->d_partials, st));
+                                       ctx->nqtiles, ctx->d_partials, ctx->qslab, st));
     HIPTRY(ctx, launch_quality_final_nc(ctx->nc, ctx->d_desc, ctx->n, ctx->d_partials, ctx->d_result,
                                         update ? ctx->d_active : nullptr, ctx->d_iters, swept, eps,
                                         update, st));
@@ -369,6 +370,8 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
         nq += d.nqtiles;
     }
     ctx->nqtiles = nq;
+    // an ensemble's tiles are several lattices end to end: plain order there
+    if (n == 1) ctx->qslab = make_slab_order(ctx->desc[0].g.st, QTILE / 2, nq);
     std::vector<int> qmap;
     for (int c = 0; c < n; c++) qmap.insert(qmap.end(), ctx->desc[c].nqtiles, c);
     if (hipMalloc(&ctx->d_desc, n * sizeof(CfgDesc)) != hipSuccess ||
@@ -845,7 +848,7 @@ namespace {
 int ensure_diff_scratch(gf_ctx *ctx) {
     const Geom &g = ctx->desc[0].g;
     // each buffer on its own, so a call after a failed allocation retries it
-    if (!ctx->d_gfield && hipMalloc(&ctx->d_gfield, 9 * (size_t)g.V * csize(ctx)) != hipSuccess) {
+    if (!ctx->d_gfield && hipMalloc(&ctx->d_gfield, (size_t)gfield_complex(g) * csize(ctx)) != hipSuccess) {
         ctx->d_gfield = nullptr;
         return fail(ctx, GF_ENOMEM, "cannot allocate the g field");
     }

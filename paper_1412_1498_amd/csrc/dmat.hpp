@@ -75,11 +75,14 @@ __device__ __forceinline__ void dm_mul_dd(const DMat &a, const DMat &b, DMat &c)
         }
 }
 
+// g(x) of site (p, h) from the g field (layout gfield_off).
 template <typename R>
-__device__ __forceinline__ void load_g(const typename V2<R>::type *__restrict__ gf, int V, int n, DMat &m) {
+__device__ __forceinline__ void load_g(const typename V2<R>::type *__restrict__ gf, const Geom &g, int p, int h,
+                                       DMat &m) {
+    const long long o = gfield_off(g, p, h, 0);
 #pragma unroll
     for (int e = 0; e < 9; e++) {
-        typename V2<R>::type v = gf[(long long)e * V + n];
+        typename V2<R>::type v = gf[o + (long long)e * BLK];
         m.re[e] = v.x;
         m.im[e] = v.y;
     }

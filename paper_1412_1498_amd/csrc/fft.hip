@@ -352,13 +352,16 @@ __device__ __forceinline__ long long spec_index(const Geom &g, int nkx, const Ro
 template <typename R, int NE>
 __global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 k_sd_delta_fx(Geom g, int nd, const typename V2<R>::type *__restrict__ Uv, FftSite f, const Cd *__restrict__ Wg,
-              typename V2<R>::type *__restrict__ spec) {
+              typename V2<R>::type *__restrict__ spec, SlabOrder so) {
     extern __shared__ Cd lds[];
     const int nx = g.nx, nc = 4 * f.ys;
     const Tile t = tile_setup(lds, Wg, nx, nc + 1, f.dnc);
     load_roots(t, Wg, nx);
     RowInfo *ri = (RowInfo *)(t.Wl + nx);
-    const long long sr0 = (long long)xcd_tile(blockIdx.x, gridDim.x) * f.ys;
+    // slab order over tiles of ys site rows: a time slice is ny nz rows, so
+    // the rows holding the t-backward links were read ny nz / ys tiles
+    // before, in the same column block
+    const long long sr0 = (long long)slab_tile(xcd_tile(blockIdx.x, gridDim.x), so) * f.ys;
     row_info(ri, g, sr0, f.ys, f.srows);
     __syncthreads();
     const gchar *U = as_global((const void *)Uv);
@@ -397,7 +400,7 @@ k_sd_delta_fx(Geom g, int nd, const typename V2<R>::type *__restrict__ Uv, FftSi
 // (the rest of each by conjugate symmetry; the imaginary parts at kx = 0 and
 // nx/2 are dropped, as for any real inverse transform), components 2c and
 // 2c + 1 travelling as Z = A + i B; then every site's step matrix
-// g = reunit(1 + i sum_a s_a lambda_a), written as the g field [e][p][h].
+// g = reunit(1 + i sum_a s_a lambda_a), written as the g field (gfield_off).
 template <typename R>
 __global__ void __launch_bounds__(FFT_BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 k_sd_fx_gfield(Geom g, FftSite f, const Cd *__restrict__ Wg, const typename V2<R>::type *__restrict__ spec,
@@ -458,13 +461,13 @@ k_sd_fx_gfield(Geom g, FftSite f, const Cd *__restrict__ Wg, const typename V2<R
         Mat<double> m;
         step_matrix(sv, m);
         const int lx = x + nx * (int)(sr0 + yl);
-        const int n = ((x + r.y + r.z + r.t) & 1) * g.Vh + (lx >> 1);
+        const long long o = gfield_off(g, (x + r.y + r.z + r.t) & 1, lx >> 1, 0);
 #pragma unroll
         for (int e = 0; e < 9; e++) {
             typename V2<R>::type v;
             v.x = (R)m.re[e];
             v.y = (R)m.im[e];
-            gf[(long long)e * g.V + n] = v;
+            gf[o + (long long)e * BLK] = v;
         }
     }
 }
@@ -624,9 +627,10 @@ hipError_t launch_sd_delta_fx(int prec, int nelem, int gauge, const Geom &g, con
     const size_t sh = site_lds_bytes(f);
     const int nd = gauge == 0 ? 4 : 3;
     const Cd *w = (const Cd *)W;
+    const SlabOrder so = make_slab_order(g.ny * g.nz, f.ys, (int)grid.x);
 #define GF_L(R, NE)                                                                                   \
     hipLaunchKernelGGL((k_sd_delta_fx<R, NE>), grid, dim3(FFT_BLOCK), sh, st, g, nd,                 \
-                       (const V2<R>::type *)U, f, w, (V2<R>::type *)spec)
+                       (const V2<R>::type *)U, f, w, (V2<R>::type *)spec, so)
     if (prec == 0) { if (nelem == 9) GF_L(double, 9); else if (nelem == 6) GF_L(double, 6); else GF_L(double, 4); }
     else { if (nelem == 9) GF_L(float, 9); else if (nelem == 6) GF_L(float, 6); else GF_L(float, 4); }
 #undef GF_L

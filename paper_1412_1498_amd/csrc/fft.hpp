@@ -68,7 +68,7 @@ hipError_t launch_fft_roots(void *W, int n, hipStream_t st);
 // Delta (eq. 3) of every site -> its components' x-transformed half spectrum
 hipError_t launch_sd_delta_fx(int prec, int nelem, int gauge, const Geom &g, const FftSite &f, const void *W,
                               const void *U, void *spec, hipStream_t st);
-// half spectrum -> inverse x transform -> g = reunit(1 + X) as the g field [e][p][h]
+// half spectrum -> inverse x transform -> g = reunit(1 + X) as the g field (gfield_off)
 hipError_t launch_sd_fx_gfield(int prec, const Geom &g, const FftSite &f, const void *W, const void *spec,
                                void *gfield, hipStream_t st);
 hipError_t launch_fft_axis(int prec, const FftAxis &f, const void *W, void *spec, int sign, int filter,

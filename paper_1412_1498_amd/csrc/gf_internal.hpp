@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "tile_order.hpp"
+
 namespace gf {
 
 // Internal link layout. Sites are split by parity p = (x+y+z+t) mod 2 and
@@ -52,6 +54,17 @@ __host__ __device__ inline long long link_off(const Geom &g, int mu, int p, int 
 
 // Complex values in one field (padding of the last block included).
 inline long long field_complex(const Geom &g) { return 2LL * g.nb * 4 * g.ne * BLK; }
+
+// The g field of a gauge transformation (9 complex elements per site, the
+// library's own scratch) in the links' blocking: the sites of one parity in
+// blocks of BLK consecutive h, each block holding element e of its BLK
+// sites contiguously. (Nine arrays of V values instead would start at
+// multiples of a large power of two, map to the same L2 sets and evict
+// each other.)
+__host__ __device__ inline long long gfield_off(const Geom &g, int p, int h, int e) {
+    return ((long long)((p * g.nb + (h >> BLK_LOG2)) * 9 + e) << BLK_LOG2) + (h & (BLK - 1));
+}
+inline long long gfield_complex(const Geom &g) { return 2LL * g.nb * 9 * BLK; }
 
 // Coordinates of site (p, h) and the half indices of its four backward
 // neighbours x - mu (which have parity 1 - p).
@@ -124,7 +137,8 @@ hipError_t launch_half_sweep(int prec, int nelem, const Schedule &s, const CfgDe
                              const int *d_tile_cfg, const int *d_active, int ntiles, int parity,
                              int reunit, hipStream_t st);
 hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int *d_qtile_cfg,
-                          const int *d_active, int nqtiles, double *d_partials, hipStream_t st);
+                          const int *d_active, int nqtiles, double *d_partials, const SlabOrder &so,
+                          hipStream_t st);
 hipError_t launch_quality_final(const CfgDesc *d_desc, int n, const double *d_partials,
                                 double *d_result, int *d_active, int *d_iters, int swept,
                                 double eps, int update_active, hipStream_t st);

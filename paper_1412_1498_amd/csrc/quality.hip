@@ -101,8 +101,8 @@ __device__ __forceinline__ void quality_tile(const CfgDesc &d, int local, double
 template <typename R, int NE>
 __global__ void __launch_bounds__(QTILE)
 k_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
-          const int *__restrict__ active, double *__restrict__ partials) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+          const int *__restrict__ active, double *__restrict__ partials, SlabOrder so) {
+    const int tile = slab_tile(xcd_tile(blockIdx.x, gridDim.x), so);
     const int c = qtile_cfg[tile];
     if (active && !active[c]) return;
     const CfgDesc d = desc[c];
@@ -221,8 +221,8 @@ hipError_t launch_quality_slices(int prec, int nelem, const CfgDesc &d, double *
 // single lattice, so the results are bitwise those of the context path.
 template <typename R, int NE>
 __global__ void __launch_bounds__(QTILE)
-k_quality_one(const CfgDesc d, double *__restrict__ partials) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+k_quality_one(const CfgDesc d, double *__restrict__ partials, SlabOrder so) {
+    const int tile = slab_tile(xcd_tile(blockIdx.x, gridDim.x), so);
     double fsum, tsum;
     quality_tile<R, NE>(d, tile, fsum, tsum);
     if (threadIdx.x == 0) {
@@ -245,7 +245,8 @@ k_quality_one_final(const CfgDesc d, const double *__restrict__ partials, double
 
 template <typename R, int NE>
 static hipError_t launch_q1(const CfgDesc &d, double *d_partials, double *d_out, hipStream_t st) {
-    hipLaunchKernelGGL((k_quality_one<R, NE>), dim3(d.nqtiles), dim3(QTILE), 0, st, d, d_partials);
+    const SlabOrder so = make_slab_order(d.g.st, QTILE / 2, d.nqtiles);
+    hipLaunchKernelGGL((k_quality_one<R, NE>), dim3(d.nqtiles), dim3(QTILE), 0, st, d, d_partials, so);
     hipLaunchKernelGGL(k_quality_one_final, dim3(1), dim3(QFINAL), 0, st, d, d_partials, d_out);
     return hipGetLastError();
 }
@@ -263,19 +264,20 @@ hipError_t launch_quality_one(int prec, int nelem, const CfgDesc &d, double *d_p
 
 template <typename R, int NE>
 static hipError_t launch_q(const CfgDesc *d_desc, const int *d_qtile_cfg, const int *d_active,
-                           int nqtiles, double *d_partials, hipStream_t st) {
+                           int nqtiles, double *d_partials, const SlabOrder &so, hipStream_t st) {
     if (nqtiles <= 0) return hipSuccess;
     hipLaunchKernelGGL((k_quality<R, NE>), dim3(nqtiles), dim3(QTILE), 0, st, d_desc, d_qtile_cfg,
-                       d_active, d_partials);
+                       d_active, d_partials, so);
     return hipGetLastError();
 }
 
 hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int *d_qtile_cfg,
-                          const int *d_active, int nqtiles, double *d_partials, hipStream_t st) {
+                          const int *d_active, int nqtiles, double *d_partials, const SlabOrder &so,
+                          hipStream_t st) {
 #define GF_Q3(R)                                                                                  \
-    (nelem == 9   ? launch_q<R, 9>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st)           \
-     : nelem == 6 ? launch_q<R, 6>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st)           \
-                  : launch_q<R, 4>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, st))
+    (nelem == 9   ? launch_q<R, 9>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, so, st)       \
+     : nelem == 6 ? launch_q<R, 6>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, so, st)       \
+                  : launch_q<R, 4>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, so, st))
     const hipError_t e = prec == 0 ? GF_Q3(double) : GF_Q3(float);
 #undef GF_Q3
     return e;
@@ -300,8 +302,8 @@ hipError_t launch_quality_final_nc(int nc, const CfgDesc *d_desc, int n, const d
 template <typename R, int N>
 __global__ void __launch_bounds__(QTILE)
 k_sun_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
-              const int *__restrict__ active, double *__restrict__ partials) {
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+              const int *__restrict__ active, double *__restrict__ partials, SlabOrder so) {
+    const int tile = slab_tile(xcd_tile(blockIdx.x, gridDim.x), so);
     const int c = qtile_cfg[tile];
     if (active && !active[c]) return;
     const CfgDesc d = desc[c];
@@ -356,11 +358,12 @@ k_sun_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cf
 }
 
 hipError_t launch_sun_quality(int prec, int nc, const CfgDesc *d_desc, const int *d_qtile_cfg,
-                              const int *d_active, int nqtiles, double *d_partials, hipStream_t st) {
+                              const int *d_active, int nqtiles, double *d_partials, const SlabOrder &so,
+                              hipStream_t st) {
     if (nqtiles <= 0) return hipSuccess;
 #define GF_Q(R, N)                                                                                 \
     hipLaunchKernelGGL((k_sun_quality<R, N>), dim3(nqtiles), dim3(QTILE), 0, st, d_desc, d_qtile_cfg, \
-                       d_active, d_partials)
+                       d_active, d_partials, so)
     if (nc == 2) { if (prec == 0) GF_Q(double, 2); else GF_Q(float, 2); }
     else if (nc == 4) { if (prec == 0) GF_Q(double, 4); else GF_Q(float, 4); }
     else return hipErrorInvalidValue;
