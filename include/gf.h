@@ -269,11 +269,15 @@ long long gf_get_sweep_count(const gf_ctx *ctx);
 
 /* ---- differentiation: F as a function of a gauge transformation ------
  * g(x) = exp(S(x)), S(x) = i sum_a s_a(x) lambda_a / 2 (Gell-Mann lambda_a,
- * Tr lambda_a lambda_b = 2 delta_ab). s is a DEVICE array of 8*V reals of
- * the context precision in layout [a][p][h] (a = generator, p, h as for the
- * links). */
+ * Tr lambda_a lambda_b = 2 delta_ab). s (and a gradient) is a DEVICE array
+ * of 8 * 2 * nb * 64 reals of the context precision in the links' blocking:
+ * component a (generator lambda_{a+1}) of site (p, h) at
+ *     ((p * nb + h / 64) * 8 + a) * 64 + h % 64,
+ * nb = ceil(V / 128) as for the links; the padding of a parity's last block
+ * is neither read nor written. */
 
-/* Convert s between the canonical layout [t][z][y][x][a] and [a][p][h]. */
+/* Convert s between the canonical layout [t][z][y][x][a] and the internal
+ * one above. */
 int gf_pack_alg(gf_ctx *ctx, const void *s_aos, void *s);
 int gf_unpack_alg(gf_ctx *ctx, const void *s, void *s_aos);
 
@@ -281,8 +285,9 @@ int gf_unpack_alg(gf_ctx *ctx, const void *s, void *s_aos);
  * Synchronises. */
 int gf_functional(gf_ctx *ctx, const void *U, const void *s, double *F);
 
-/* grad[a][p][h] = dF * dF_U[g]/ds_a(x) at s: the su(3)-valued gradient of
- * eq. (1) with respect to the gauge transformation. Asynchronous. */
+/* grad = dF * dF_U[g]/ds_a(x) at s, in the layout of s: the su(3)-valued
+ * gradient of eq. (1) with respect to the gauge transformation.
+ * Asynchronous. */
 int gf_functional_grad(gf_ctx *ctx, const void *U, const void *s, double dF, void *grad);
 
 /* Apply g = exp(S(s)): U_mu(x) <- g(x) U_mu(x) g(x + mu)^dagger for all mu.

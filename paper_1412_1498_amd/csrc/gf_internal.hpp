@@ -66,6 +66,13 @@ __host__ __device__ inline long long gfield_off(const Geom &g, int p, int h, int
 }
 inline long long gfield_complex(const Geom &g) { return 2LL * g.nb * 9 * BLK; }
 
+// An su(3) algebra field (8 reals per site: s_a(x), or a gradient) in the
+// same blocking: component a of site (p, h).
+__host__ __device__ inline long long alg_off(const Geom &g, int p, int h, int a) {
+    return ((long long)((p * g.nb + (h >> BLK_LOG2)) * 8 + a) << BLK_LOG2) + (h & (BLK - 1));
+}
+inline long long alg_reals(const Geom &g) { return 2LL * g.nb * 8 * BLK; }
+
 // Coordinates of site (p, h) and the half indices of its four backward
 // neighbours x - mu (which have parity 1 - p).
 struct SiteNbr {

@@ -89,10 +89,12 @@ __device__ void dm_exp(const DMat &S, DMat &E) {
     }
 }
 
+// s_a(x) of site (p, h) (layout alg_off).
 template <typename R>
-__device__ __forceinline__ void load_s(const R *__restrict__ s, int V, int n, double out[8]) {
+__device__ __forceinline__ void load_s(const R *__restrict__ s, const Geom &g, int p, int h, double out[8]) {
+    const long long o = alg_off(g, p, h, 0);
 #pragma unroll
-    for (int a = 0; a < 8; a++) out[a] = (double)s[(long long)a * V + n];
+    for (int a = 0; a < 8; a++) out[a] = (double)s[o + (long long)a * BLK];
 }
 
 // g field (9 complex per site, layout gfield_off) from s.
@@ -102,7 +104,7 @@ __global__ void __launch_bounds__(256) k_expS(Geom g, const R *__restrict__ s, t
     if (n >= g.V) return;
     const int p = n >= g.Vh, h = n - p * g.Vh;
     double sv[8];
-    load_s(s, g.V, n, sv);
+    load_s(s, g, p, h, sv);
     DMat S, E;
     algebra_matrix(sv, S);
     // the g field is stored in R: degree 8 is exact to float rounding, 15 to double
@@ -229,32 +231,37 @@ __global__ void __launch_bounds__(DT_TILE) k_functional_grad(Geom g, const typen
                                   double scale, SlabOrder so, R *__restrict__ grad) {
     int p, h;
     if (!tile_site(g, so, p, h)) return;
-    const int n = p * g.Vh + h;
     const SiteNbr fw = site_fwd_neighbours(g, p, h);
     const SiteNbr bw = site_neighbours(g, p, h);
+    // The site's own s and g first, then the staple from t and z down to x:
+    // the t and z neighbours' links and g lie in other tiles, and the earlier
+    // in a workgroup's life they are read, the fewer tiles have passed
+    // through L2 since their own workgroups read them (the x and y
+    // neighbours mostly lie in this tile).
+    double sv[8];
+    load_s(s, g, p, h, sv);
+    DMat gx;
+    load_g<R>(gf, g, p, h, gx);
     DMat K;
 #pragma unroll
     for (int e = 0; e < 9; e++) { K.re[e] = 0.0; K.im[e] = 0.0; }
 #pragma unroll
-    for (int mu = 0; mu < ND; mu++) {
+    for (int mu = ND - 1; mu >= 0; mu--) {
         DMat u, gy, t;
-        // U_mu(x) g(x+mu)^dagger
-        load_u<R, NE>(U, link_off(g, mu, p, h), u);
-        load_g<R>(gf, g, 1 - p, pick4(fw.hb, mu), gy);
-        dm_mul_nd(u, gy, t);
-#pragma unroll
-        for (int e = 0; e < 9; e++) { K.re[e] += t.re[e]; K.im[e] += t.im[e]; }
         // U_mu(x-mu)^dagger g(x-mu)^dagger
         load_u<R, NE>(U, link_off(g, mu, 1 - p, pick4(bw.hb, mu)), u);
         load_g<R>(gf, g, 1 - p, pick4(bw.hb, mu), gy);
         dm_mul_dd(u, gy, t);
 #pragma unroll
         for (int e = 0; e < 9; e++) { K.re[e] += t.re[e]; K.im[e] += t.im[e]; }
+        // U_mu(x) g(x+mu)^dagger
+        load_u<R, NE>(U, link_off(g, mu, p, h), u);
+        load_g<R>(gf, g, 1 - p, pick4(fw.hb, mu), gy);
+        dm_mul_nd(u, gy, t);
+#pragma unroll
+        for (int e = 0; e < 9; e++) { K.re[e] += t.re[e]; K.im[e] += t.im[e]; }
     }
-    double sv[8];
-    load_s(s, g.V, n, sv);
-    DMat gx, Y;
-    load_g<R>(gf, g, p, h, gx);
+    DMat Y;
     dm_mul(K, gx, Y);  // K e^S
     // Only the anti-hermitian traceless part of Y reaches the traces, and
     // ad_S maps that part to itself, so the series runs on its components:
@@ -283,8 +290,9 @@ __global__ void __launch_bounds__(DT_TILE) k_functional_grad(Geom g, const typen
         if (tmax <= tol * amax) break;
     }
     const double c = scale / (2.0 * ND * 3.0 * (double)g.V);
+    const long long o = alg_off(g, p, h, 0);
 #pragma unroll
-    for (int a = 0; a < 8; a++) grad[(long long)a * g.V + n] = (R)(-tr[a] * c);
+    for (int a = 0; a < 8; a++) grad[o + (long long)a * BLK] = (R)(-tr[a] * c);
 }
 
 // U_mu(x) <- g(x) U_mu(x) g(x+mu)^dagger for all four mu. A workgroup takes
@@ -330,7 +338,7 @@ hipError_t launch_expS(int prec, const Geom &g, const void *s, void *gfield, hip
 hipError_t launch_functional(int prec, int nelem, int gauge, const Geom &g, const void *U,
                              const void *gfield, double *d_partials, hipStream_t st) {
     const dim3 grid((g.Vh + DT_TILE / 2 - 1) / (DT_TILE / 2));
-    const SlabOrder so = make_slab_order(g.st, DT_TILE / 2, (int)grid.x);
+    const SlabOrder so = make_slab_order(g.st, DT_TILE / 2, (int)grid.x, 64);
 #define GF_L(R, NE)                                                                               \
     do {                                                                                          \
         if (gauge == 0)                                                                           \
@@ -355,7 +363,7 @@ hipError_t launch_functional_grad(int prec, int nelem, int gauge, const Geom &g,
                                   const void *s, const void *gfield, double scale, void *grad,
                                   hipStream_t st) {
     const dim3 grid((g.Vh + DT_TILE / 2 - 1) / (DT_TILE / 2));
-    const SlabOrder so = make_slab_order(g.st, DT_TILE / 2, (int)grid.x);
+    const SlabOrder so = make_slab_order(g.st, DT_TILE / 2, (int)grid.x, 64);
 #define GF_L(R, NE)                                                                               \
     do {                                                                                          \
         if (gauge == 0)                                                                           \
@@ -376,7 +384,7 @@ hipError_t launch_functional_grad(int prec, int nelem, int gauge, const Geom &g,
 hipError_t launch_gauge_transform(int prec, int nelem, const Geom &g, void *U, const void *gfield,
                                   hipStream_t st) {
     const dim3 grid((g.Vh + GT_TILE / 2 - 1) / (GT_TILE / 2));
-    const SlabOrder so = make_slab_order(g.st, GT_TILE / 2, (int)grid.x);
+    const SlabOrder so = make_slab_order(g.st, GT_TILE / 2, (int)grid.x, 64);
 #define GF_L(R, NE)                                                                               \
     hipLaunchKernelGGL((k_gauge_transform<R, NE>), grid, dim3(GT_TILE), 0, st, g, (V2<R>::type *)U, \
                        (const V2<R>::type *)gfield, so)

@@ -69,12 +69,12 @@ __global__ void __launch_bounds__(256) k_pack_alg(Geom g, const R *__restrict__ 
     const int t = n / (g.nx * g.ny * g.nz);
     int p, h;
     site_to_ph(g, x, y, z, t, p, h);
-    const int off = p * g.Vh + h;
+    const long long off = alg_off(g, p, h, 0);
     R *a = const_cast<R *>(aos) + 8LL * n;
 #pragma unroll
     for (int k = 0; k < 8; k++) {
-        if (!unpack) s[(long long)k * g.V + off] = a[k];
-        else a[k] = s[(long long)k * g.V + off];
+        if (!unpack) s[off + (long long)k * BLK] = a[k];
+        else a[k] = s[off + (long long)k * BLK];
     }
 }
 

@@ -340,11 +340,15 @@ class Context:
 
     # -- differentiation ---------------------------------------------------------
     def empty_alg(self, device="cuda"):
-        return torch.empty((8, 2, self.volume() // 2), dtype=self.rdtype, device=device)
+        """An algebra field in the internal layout, shape (2, nb, 8, 64):
+        [parity][block of 64 sites][component a][site in block]; the padding
+        of the last block is zero (the kernels never write it)."""
+        return torch.zeros((2, self.blocks(), 8, 64), dtype=self.rdtype, device=device)
 
     def _check_alg(self, s):
-        if s.dtype != self.rdtype or s.numel() != 8 * self.volume():
-            raise ValueError(f"algebra field must be {self.rdtype} with {8 * self.volume()} elements")
+        n = 2 * self.blocks() * 8 * 64
+        if s.dtype != self.rdtype or s.numel() != n:
+            raise ValueError(f"algebra field must be {self.rdtype} with {n} elements (2 x nb x 8 x 64)")
         return _ptr(s)
 
     def pack_alg(self, s_aos):
@@ -368,7 +372,7 @@ class Context:
 
     def functional_grad(self, U, s, dF=1.0, out=None):
         if out is None:
-            out = torch.empty_like(s)
+            out = torch.zeros_like(s)
         self._check(lib.gf_functional_grad(self._h, ctypes.c_void_p(self._check_field(U)),
                                            ctypes.c_void_p(self._check_alg(s)), float(dF),
                                            ctypes.c_void_p(self._check_alg(out))))
