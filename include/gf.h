@@ -128,6 +128,10 @@ typedef struct gf_params {
                                began. The context copies the path at creation
                                and opens the file (append) on first use;
                                flushed after every check. */
+    int tile_order;         /* order in which a half-sweep's workgroups take
+                               their tiles: 0 dispatch order, 1 XCD-contiguous
+                               shares; -1 = default (0). Results do not depend
+                               on it. */
 } gf_params;
 
 /* Fill *p with the defaults for precision prec. */
@@ -245,7 +249,7 @@ int gf_batch_fix(gf_ctx *ctx, void *const *U, const double *omega, double eps, i
 int gf_batch_quality(gf_ctx *ctx, void *const *U, double *F, double *theta);
 
 /* Time the candidate schedules (lanes per site, workgroup size,
- * non-temporal access) on a scratch copy of the members' fields U[i] and
+ * non-temporal access, and for a single lattice the tile order) on a scratch copy of the members' fields U[i] and
  * keep the fastest in ctx. Every schedule gives bitwise the same links. If
  * cache_path is not NULL, a previous result for the same device, library
  * sources, colour number, precision, storage and lattice list is reused and
@@ -255,9 +259,10 @@ int gf_batch_quality(gf_ctx *ctx, void *const *U, double *F, double *theta);
  * (and frees) a scratch copy of the fields. Synchronises. */
 int gf_autotune(gf_ctx *ctx, void *const *U, double omega, const char *cache_path);
 
-/* The schedule in use: lanes per site, workgroup threads and the
- * non-temporal flag. */
-int gf_get_schedule(const gf_ctx *ctx, int *lanes_per_site, int *block_threads, int *nontemporal);
+/* The schedule in use: lanes per site, workgroup threads, the
+ * non-temporal flag and the tile order (NULL outputs are skipped). */
+int gf_get_schedule(const gf_ctx *ctx, int *lanes_per_site, int *block_threads, int *nontemporal,
+                    int *tile_order);
 
 /* Total device time (ms) and number of the half-sweep launches timed since
  * the last call (needs gf_params.timing = 1). Synchronises. */

@@ -185,6 +185,7 @@ Schedule default_schedule(int prec, int nc, const gf_params &p) {
     s.block = p.block_threads > 0 ? p.block_threads
                                    : ((prec == GF_F32 && p.storage != GF_STORE_18) ? 256 : 128);
     s.nt = p.nontemporal >= 0 ? p.nontemporal : 1;
+    s.order = p.tile_order >= 0 ? p.tile_order : 0;
     return s;
 }
 
@@ -194,6 +195,7 @@ int check_schedule(gf_ctx *ctx, const Schedule &s, int nc) {
     CHECK(ctx, nc != 4 || s.lps >= 2, GF_EINVAL, "SU(4) links need lanes_per_site >= 2");
     CHECK(ctx, s.block >= 64 && s.block <= 256 && s.block % 64 == 0, GF_EINVAL,
           "block_threads = %d must be 64, 128, 192 or 256", s.block);
+    CHECK(ctx, s.order == 0 || s.order == 1, GF_EINVAL, "tile_order = %d must be 0 or 1", s.order);
     return GF_OK;
 }
 
@@ -424,6 +426,7 @@ void gf_params_default(gf_params *p, int prec) {
     p->start_sweep = 0;
     p->storage = GF_STORE_18;
     p->nontemporal = -1;
+    p->tile_order = -1;
 }
 
 int gf_create(gf_ctx **out, const int dims[4], int nc, int gauge, int prec, void *stream,
@@ -705,11 +708,12 @@ int gf_batch_fix(gf_ctx *ctx, void *const *U, const double *omega, double eps, i
     return all ? GF_OK : GF_NOT_CONVERGED;
 }
 
-int gf_get_schedule(const gf_ctx *ctx, int *lps, int *block, int *nt) {
+int gf_get_schedule(const gf_ctx *ctx, int *lps, int *block, int *nt, int *tile_order) {
     if (!ctx) return GF_EINVAL;
     if (lps) *lps = ctx->sched.lps;
     if (block) *block = ctx->sched.block;
     if (nt) *nt = ctx->sched.nt;
+    if (tile_order) *tile_order = ctx->sched.order;
     return GF_OK;
 }
 
@@ -767,7 +771,7 @@ int gf_autotune(gf_ctx *ctx, void *const *U, double omega, const char *cache_pat
         if (!found.empty()) {
             Schedule s{};
             std::istringstream is(found);
-            if (is >> s.lps >> s.block >> s.nt && check_schedule(ctx, s, ctx->nc) == GF_OK) {
+            if (is >> s.lps >> s.block >> s.nt >> s.order && check_schedule(ctx, s, ctx->nc) == GF_OK) {
                 ctx->sched = s;
                 return build_tiles(ctx);
             }
@@ -808,8 +812,13 @@ int gf_autotune(gf_ctx *ctx, void *const *U, double omega, const char *cache_pat
     const int block_list[] = {64, 128, 256};
     for (int li = 0; li < 4 && rc == GF_OK; li++)
         for (int bi = 0; bi < 3 && rc == GF_OK; bi++)
-                for (int nt = 0; nt < 2 && rc == GF_OK; nt++) {
-                    Schedule s{lps_list[li], block_list[bi], nt};
+            for (int nt = 0; nt < 2 && rc == GF_OK; nt++)
+                // XCD-contiguous shares only for a single lattice: in an ensemble the
+                // members that converge first leave their XCDs' shares empty while the
+                // others still carry the large members' tiles (measured on the uneven
+                // ensemble: tuned with every member active it won, then ran 11 % slower)
+                for (int order = 0; order < (ctx->n == 1 ? 2 : 1) && rc == GF_OK; order++) {
+                    Schedule s{lps_list[li], block_list[bi], nt, order};
                     if (ctx->nc == 4 && s.lps < 2) continue;       // registers
                     if (ctx->nc != 3 && nt != 1) continue;         // SU(N) links are always non-temporal
                     ctx->sched = s;
@@ -835,7 +844,7 @@ int gf_autotune(gf_ctx *ctx, void *const *U, double omega, const char *cache_pat
     if (rc2) return rc2;
     if (cache_path) {
         std::ofstream outf(cache_path, std::ios::app);
-        outf << k << " " << best.lps << " " << best.block << " " << best.nt << " "
+        outf << k << " " << best.lps << " " << best.block << " " << best.nt << " " << best.order << " "
              << best_ms / 6.0f << "\n";
     }
     return GF_OK;

@@ -137,6 +137,7 @@ struct Schedule {
     int lps;        // lanes per site: 1, 2, 4, 8
     int block;      // threads per workgroup
     int nt;         // non-temporal loads/stores
+    int order;      // sweep tiles: 0 in dispatch order, 1 XCD-contiguous (xcd_tile)
 };
 
 // ---- launchers (defined in the .hip files) ----

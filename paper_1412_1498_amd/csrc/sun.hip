@@ -195,8 +195,8 @@ __device__ __forceinline__ void or_site_n(const CfgDesc &d, int p, int h, int su
 template <typename R, int N, int LPS, bool RU>
 __global__ void __launch_bounds__(256)
 k_sun_half_sweep(const CfgDesc *__restrict__ desc, const int *__restrict__ tile_cfg,
-                 const int *__restrict__ active, int parity) {
-    const int tile = blockIdx.x;
+                 const int *__restrict__ active, int parity, int order) {
+    const int tile = order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int c = tile_cfg[tile];
     if (!active[c]) return;
     const CfgDesc d = desc[c];
@@ -211,10 +211,10 @@ hipError_t launch_sun_t(const Schedule &s, const CfgDesc *d_desc, const int *d_t
     if (ntiles <= 0) return hipSuccess;
     if (reunit)
         hipLaunchKernelGGL((k_sun_half_sweep<R, N, LPS, true>), dim3(ntiles), dim3(s.block), 0, st,
-                           d_desc, d_tile_cfg, d_active, parity);
+                           d_desc, d_tile_cfg, d_active, parity, s.order);
     else
         hipLaunchKernelGGL((k_sun_half_sweep<R, N, LPS, false>), dim3(ntiles), dim3(s.block), 0, st,
-                           d_desc, d_tile_cfg, d_active, parity);
+                           d_desc, d_tile_cfg, d_active, parity, s.order);
     return hipGetLastError();
 }
 

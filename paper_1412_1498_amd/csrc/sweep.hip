@@ -228,8 +228,9 @@ __device__ __forceinline__ void or_site(const CfgDesc &d, int p, int h, int sub)
 template <typename R, int NE, int LPS, bool NT, bool RU>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu((NE == 4 && sizeof(R) == 4) ? GF_SWEEP8_WAVES : 1)))
 k_half_sweep(const CfgDesc *__restrict__ desc, const int *__restrict__ tile_cfg,
-             const int *__restrict__ active, int parity) {
-    const int tile = blockIdx.x;
+             const int *__restrict__ active, int parity, int order) {
+    // the tile order is a schedule choice: every tile is independent
+    const int tile = order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
     const int c = tile_cfg[tile];
     if (!active[c]) return;
     const CfgDesc d = desc[c];
@@ -244,10 +245,10 @@ static hipError_t launch_t(const Schedule &s, const CfgDesc *d_desc, const int *
     if (ntiles <= 0) return hipSuccess;
     if (reunit)
         hipLaunchKernelGGL((k_half_sweep<R, NE, LPS, NT, true>), dim3(ntiles), dim3(s.block), 0, st,
-                           d_desc, d_tile_cfg, d_active, parity);
+                           d_desc, d_tile_cfg, d_active, parity, s.order);
     else
         hipLaunchKernelGGL((k_half_sweep<R, NE, LPS, NT, false>), dim3(ntiles), dim3(s.block), 0, st,
-                           d_desc, d_tile_cfg, d_active, parity);
+                           d_desc, d_tile_cfg, d_active, parity, s.order);
     return hipGetLastError();
 }
 

@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("use_graph", ctypes.c_int),
         ("timing", ctypes.c_int),
         ("log_path", ctypes.c_char_p),
+        ("tile_order", ctypes.c_int),
     ]
 
 
@@ -78,7 +79,7 @@ def _load():
         "gf_batch_fix": (I, [P, P, P, D, I, P, P, P]),
         "gf_batch_quality": (I, [P, P, P, P]),
         "gf_autotune": (I, [P, P, D, ctypes.c_char_p]),
-        "gf_get_schedule": (I, [P, P, P, P]),
+        "gf_get_schedule": (I, [P, P, P, P, P]),
         "gf_timing": (I, [P, P, P]),
         "gf_set_sweep_count": (I, [P, LL]),
         "gf_get_sweep_count": (LL, [P]),
@@ -321,9 +322,10 @@ class Context:
         return self.schedule()
 
     def schedule(self):
-        v = [ctypes.c_int() for _ in range(3)]
+        v = [ctypes.c_int() for _ in range(4)]
         self._check(lib.gf_get_schedule(self._h, *[ctypes.byref(x) for x in v]))
-        return dict(lanes_per_site=v[0].value, block_threads=v[1].value, nontemporal=v[2].value)
+        return dict(lanes_per_site=v[0].value, block_threads=v[1].value, nontemporal=v[2].value,
+                    tile_order=v[3].value)
 
     def timing(self):
         ms, n = ctypes.c_double(), ctypes.c_longlong()

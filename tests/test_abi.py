@@ -63,6 +63,9 @@ def test_invalid_arguments_fail_before_device_use(gf):
     bad = gf.default_params(gf.F32, block_threads=100)
     assert gf.lib.gf_create(ctypes.byref(h), gf._dims_arr((4, 4, 4, 4)), 3, 0, gf.F32, None,
                             ctypes.byref(bad)) == gf.EINVAL
+    bad = gf.default_params(gf.F32, tile_order=2)
+    assert gf.lib.gf_create(ctypes.byref(h), gf._dims_arr((4, 4, 4, 4)), 3, 0, gf.F32, None,
+                            ctypes.byref(bad)) == gf.EINVAL
     # every entry point tolerates a NULL context
     assert gf.lib.gf_destroy(None) == gf.OK
     assert gf.lib.gf_sweep(None, None, 0, 1.7) == gf.EINVAL

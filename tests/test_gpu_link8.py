@@ -96,15 +96,15 @@ def test_all_schedules_give_identical_bits(gf, field_cache, prec):
     ref = None
     for lps in (1, 2, 4, 8):
         for block in (64, 128, 256):
-            for nt in (0, 1):
+            for nt, order in ((0, 0), (1, 1)):
                 ctx = make_ctx(gf, dims, LANDAU, prec, lanes_per_site=lps, block_threads=block,
-                               nontemporal=nt, reunit_every=2)
+                               nontemporal=nt, tile_order=order, reunit_every=2)
                 Ug = to_gpu(ctx, U)
                 ctx.sweeps(Ug, 1.7, 3)
                 if ref is None:
                     ref = Ug.clone()
                 else:
-                    assert torch.equal(Ug, ref), (lps, block, nt)
+                    assert torch.equal(Ug, ref), (lps, block, nt, order)
 
 
 @pytest.mark.parametrize("prec", [0, 1])

@@ -156,16 +156,16 @@ def test_all_schedules_give_identical_bits(gf, field_cache, prec, storage):
     ref = None
     for lps in (1, 2, 4, 8):
         for block in (64, 128, 192, 256):
-            for nt in (0, 1):
+            for nt, order in ((0, 0), (1, 0), (1, 1), (0, 1)):
                 ctx = make_ctx(gf, dims, LANDAU, prec, lanes_per_site=lps, block_threads=block,
-                               nontemporal=nt, storage=storage, reunit_every=2)
+                               nontemporal=nt, tile_order=order, storage=storage, reunit_every=2)
                 Ug = to_gpu(ctx, U)
                 ctx.sweeps(Ug, 1.7, 3)
                 out = Ug.cpu()
                 if ref is None:
                     ref = out
                 else:
-                    assert torch.equal(out, ref), (lps, block, nt)
+                    assert torch.equal(out, ref), (lps, block, nt, order)
 
 
 @pytest.mark.parametrize("gauge", [LANDAU, COULOMB])
@@ -410,6 +410,7 @@ def test_autotune_keeps_bits_and_caches(gf, field_cache, tmp_path):
     cache = str(tmp_path / "tune.txt")
     s1 = ens.autotune(Us, 1.7, cache)
     assert s1["lanes_per_site"] in (1, 2, 4, 8) and s1["block_threads"] in (64, 128, 256)
+    assert s1["tile_order"] in (0, 1)
     for u, r in zip(Us, ref):  # tuning ran on scratch copies
         assert torch.equal(u, r)
     rb = ens.batch_fix(Us, 1.7, 0.0, 7)

@@ -120,7 +120,8 @@ def test_all_schedules_give_identical_bits(gf, n, prec):
     ref = None
     for lps in LPS[n]:
         for block in (64, 128, 256):
-            ctx = ctx_of(gf, dims, n, LANDAU, prec, lanes_per_site=lps, block_threads=block, reunit_every=2)
+            ctx = ctx_of(gf, dims, n, LANDAU, prec, lanes_per_site=lps, block_threads=block,
+                         tile_order=block % 128 // 64, reunit_every=2)
             Ug = to_gpu(ctx, U)
             ctx.sweeps(Ug, 1.7, 3)
             if ref is None:
