@@ -337,7 +337,7 @@ def run_cpu_baseline(gf, synth, torch, fields, main_name, gpu_value, gpu_fp64_ti
     share = min(16, len(os.sched_getaffinity(0)))
     before = oracle.set_threads(0)
     runs = []
-    plan = [(1, "32x32x32x32", 3), (share, "32x32x32x32", 5), (share, main_name, 5)]
+    plan = [(1, "32x32x32x32", 5), (share, "32x32x32x32", 5), (share, main_name, 5)]
     for threads, name, nsw in plan:
         Uh, dims = fields[name]
         A = Uh.copy()
