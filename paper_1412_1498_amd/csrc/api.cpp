@@ -49,7 +49,8 @@ struct gf_ctx {
     int ntiles = 0;
     int *d_qtile_cfg = nullptr;
     int nqtiles = 0;
-    SlabOrder qslab{0, 0, 0};        // quality tile order (single lattices only)
+    SlabOrder qslab{0, 0, 0, 0, 0};  // quality tile order (single lattices only)
+    bool qstream = false;            // F/theta by k_quality_tstream (single SU(3) lattices)
     double *d_partials = nullptr;
     double *d_result = nullptr;      // 2 per member
     int *d_active = nullptr;         // per member (batch driver)
@@ -298,7 +299,10 @@ int full_sweeps(gf_ctx *ctx, int n, const int *d_active, hipStream_t st) {
 }
 
 int quality_launch(gf_ctx *ctx, const int *d_active, int update, int swept, double eps, hipStream_t st) {
-    if (ctx->nc == 3)
+    if (ctx->qstream)
+        HIPTRY(ctx, launch_quality_tstream(ctx->prec, ctx->nelem, ctx->desc[0].g, ctx->d_desc, d_active,
+                                           ctx->d_partials, st));
+    else if (ctx->nc == 3)
         HIPTRY(ctx, launch_quality(ctx->prec, ctx->nelem, ctx->d_desc, ctx->d_qtile_cfg, d_active,
                                    ctx->nqtiles, ctx->d_partials, ctx->qslab, st));
     else
@@ -373,7 +377,13 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
     }
     ctx->nqtiles = nq;
     // an ensemble's tiles are several lattices end to end: plain order there
-    if (n == 1) ctx->qslab = make_slab_order(ctx->desc[0].g.st, QTILE / 2, nq);
+    if (n == 1) {
+        const Geom &g0 = ctx->desc[0].g;
+        const int nd = ctx->desc[0].gauge == GF_LANDAU ? 4 : 3;
+        const long long tile_bytes = (long long)QTILE * nd * ctx->nelem * 2 * (prec == GF_F64 ? 8 : 4);
+        ctx->qslab = pick_slab_order(g0.st, g0.sz, g0.hx, g0.nz, QTILE / 2, nq, tile_bytes);
+    }
+    ctx->qstream = n == 1 && ctx->nc == 3 && prec == GF_F64 && quality_tstream_ok(ctx->desc[0].g);
     std::vector<int> qmap;
     for (int c = 0; c < n; c++) qmap.insert(qmap.end(), ctx->desc[c].nqtiles, c);
     if (hipMalloc(&ctx->d_desc, n * sizeof(CfgDesc)) != hipSuccess ||

@@ -153,6 +153,11 @@ hipError_t launch_quality_final(const CfgDesc *d_desc, int n, const double *d_pa
 // Per-time-slice F_t and theta_t of one member into d_out[2 t], d_out[2 t + 1];
 // d_partials holds 2 * nt * quality_slice_chunks(g) doubles.
 int quality_slice_chunks(const Geom &g);
+// k_quality for a single lattice whose time slices split into whole tiles,
+// walking runs of slices (same partials as launch_quality)
+bool quality_tstream_ok(const Geom &g);
+hipError_t launch_quality_tstream(int prec, int nelem, const Geom &g, const CfgDesc *d_desc, const int *d_active,
+                                  double *d_partials, hipStream_t st);
 hipError_t launch_quality_slices(int prec, int nelem, const CfgDesc &d, double *d_partials, double *d_out,
                                  hipStream_t st);
 // F and theta of one lattice given by value (d.qtile0 = 0, d.nqtiles tiles):

@@ -2,7 +2,8 @@
 // reduced in double in a fixed order.
 //
 // Stage 1: one workgroup per tile of QTILE sites: the QTILE/2 half-indices
-// h of the tile, both parities (lanes [0, QTILE/2) even, the rest odd). A
+// h of the tile, both parities (each wave 32 half indices, even sites in its
+// lower and odd sites in its upper 32 lanes). A
 // site's backward links belong to the other parity at nearby h (x, y, z
 // neighbours), so the tile's own forward reads bring most of them into
 // cache; tiles are also handed out so that each XCD walks one contiguous
@@ -16,6 +17,8 @@
 // partials, strided per lane then by the same fixed butterfly, and
 // normalises. Neither stage
 // depends on the sweep schedule, so F and theta are bitwise reproducible.
+#include <algorithm>
+
 #include "su3_device.hpp"
 #include "sun_device.hpp"
 #include "sun_internal.hpp"
@@ -48,10 +51,14 @@ __device__ __forceinline__ void block_sum2(double &a, double &b) {
 }
 
 // Sums of Re Tr over the functional's forward links and of Tr Delta
-// Delta^dagger at site (p, h), added to fsum / tsum (all in double).
-template <typename R, int NE>
+// Delta^dagger at site (p, h), added to fsum / tsum (all in double). With TC
+// (the slice-streaming kernel), tl carries the t links: on entry, when
+// have_bt, the site's backward t link (taken instead of loading it); on exit,
+// the site's forward t link.
+template <typename R, int NE, bool TC = false>
 __device__ __forceinline__ void site_quality(const Geom &g, const gchar *U, int gauge, int p, int h,
-                                             double &fsum, double &tsum) {
+                                             double &fsum, double &tsum, bool have_bt = false,
+                                             Mat<R> *tl = nullptr) {
     const int nd = gauge == 0 ? 4 : 3;
     const SiteNbr nb = site_neighbours(g, p, h);
     double mr[9], mi[9];
@@ -60,7 +67,13 @@ __device__ __forceinline__ void site_quality(const Geom &g, const gchar *U, int 
     for (int mu = 0; mu < nd; mu++) {
         Mat<R> f, b;
         load_link<R, NE, false>(f, U, link_off(g, mu, p, h));
-        load_link<R, NE, false>(b, U, link_off(g, mu, 1 - p, pick4(nb.hb, mu)));
+        if constexpr (TC) {
+            if (mu == 3 && have_bt) b = *tl;
+            else load_link<R, NE, false>(b, U, link_off(g, mu, 1 - p, pick4(nb.hb, mu)));
+            if (mu == 3) *tl = f;
+        } else {
+            load_link<R, NE, false>(b, U, link_off(g, mu, 1 - p, pick4(nb.hb, mu)));
+        }
         fsum += (double)f.re[0] + (double)f.re[4] + (double)f.re[8];
 #pragma unroll
         for (int e = 0; e < 9; e++) {
@@ -85,13 +98,22 @@ __device__ __forceinline__ void site_quality(const Geom &g, const gchar *U, int 
     for (int e = 0; e < 9; e++) tsum += ar[e] * ar[e] + ai[e] * ai[e];
 }
 
+// Half offset within a tile and parity of lane `lane` of a tile: wave w
+// takes half indices [32 w, 32 w + 32) of the tile, its lanes 0-31 the even
+// and 32-63 the odd sites (so every 16 lanes read whole 128-byte lines, and
+// the sites of lanes l and l ^ 32 are the even and odd site of one half
+// index).
+__device__ __forceinline__ int qlane_offset(int lane) { return (lane >> 6) * 32 + (lane & 31); }
+__device__ __forceinline__ int qlane_parity(int lane) { return (lane >> 5) & 1; }
+
 // Partial pair of quality tile `local` of member d (QTILE/2 half indices,
-// both parities), summed over the workgroup: result in lane 0.
+// both parities, lanes as qlane_offset / qlane_parity), summed over the
+// workgroup: result in lane 0.
 template <typename R, int NE>
 __device__ __forceinline__ void quality_tile(const CfgDesc &d, int local, double &fsum, double &tsum) {
     constexpr int QH = QTILE / 2;
-    const int p = threadIdx.x >= QH;
-    const int h = local * QH + (int)threadIdx.x - p * QH;
+    const int p = qlane_parity(threadIdx.x);
+    const int h = local * QH + qlane_offset(threadIdx.x);
     fsum = 0.0;
     tsum = 0.0;
     if (h < d.g.Vh) site_quality<R, NE>(d.g, as_global(d.U), d.gauge, p, h, fsum, tsum);
@@ -111,6 +133,63 @@ k_quality(const CfgDesc *__restrict__ desc, const int *__restrict__ qtile_cfg,
     if (threadIdx.x == 0) {
         partials[2 * tile] = fsum;
         partials[2 * tile + 1] = tsum;
+    }
+}
+
+// Slice-streaming form of k_quality for one lattice whose time slices split
+// into whole tiles (st a multiple of QTILE/2, nchunk = st / (QTILE/2) tiles a
+// slice). Workgroup b takes chunk `chunk` of the trun consecutive slices of
+// run `run` and writes, slice by slice, the partial pair of tile
+// t * nchunk + chunk: the same sites, lane mapping and sums as k_quality, so
+// the partials are bitwise those of k_quality. The backward t link of a site
+// is the forward t link of the opposite-parity site of the same half offset
+// in the previous slice, which the partner lane (lane ^ 32) loaded there: it
+// is passed across the lane pair instead of being loaded again (only the
+// run's first slice loads it). The per-slice workgroup sum keeps the four
+// waves of a workgroup on the same slice (without it they drift apart and
+// re-read more of each other's x and y neighbours).
+template <typename R, int NE>
+__global__ void __launch_bounds__(QTILE)
+k_quality_tstream(const CfgDesc *__restrict__ desc, const int *__restrict__ active, int nchunk, int trun,
+                  double *__restrict__ partials) {
+    constexpr int NW = QTILE / 64;
+    __shared__ double sa[2][NW], sb[2][NW];
+    if (active && !active[0]) return;
+    const CfgDesc d = desc[0];
+    const Geom &g = d.g;
+    const gchar *U = as_global(d.U);
+    const int b = xcd_tile(blockIdx.x, gridDim.x);
+    const int run = b / nchunk, chunk = b - run * nchunk;
+    const int p = qlane_parity(threadIdx.x);
+    const int o = chunk * (QTILE / 2) + qlane_offset(threadIdx.x);
+    const int t0 = run * trun, nts = min(trun, g.nt - t0);
+    const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+    Mat<R> tl;
+    for (int i = 0; i < nts; i++) {
+        const bool have_bt = d.gauge == 0 && i > 0;
+        if (have_bt) {
+#pragma unroll
+            for (int e = 0; e < 9; e++) {
+                tl.re[e] = __shfl_xor(tl.re[e], 32);
+                tl.im[e] = __shfl_xor(tl.im[e], 32);
+            }
+        }
+        double fsum = 0.0, tsum = 0.0;
+        site_quality<R, NE, true>(g, U, d.gauge, p, (t0 + i) * g.st + o, fsum, tsum, have_bt, &tl);
+        // block_sum2's order, into alternating buffers: the buffer written
+        // here is next written two slices on, after another barrier
+        const int buf = i & 1;
+        fsum = wave_sum(fsum);
+        tsum = wave_sum(tsum);
+        if (lane == 0) { sa[buf][wid] = fsum; sb[buf][wid] = tsum; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double ta = 0.0, tb = 0.0;
+            for (int w = 0; w < NW; w++) { ta += sa[buf][w]; tb += sb[buf][w]; }
+            const size_t tile = (size_t)(t0 + i) * nchunk + chunk;
+            partials[2 * tile] = ta;
+            partials[2 * tile + 1] = tb;
+        }
     }
 }
 
@@ -280,6 +359,38 @@ hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int 
                   : launch_q<R, 4>(d_desc, d_qtile_cfg, d_active, nqtiles, d_partials, so, st))
     const hipError_t e = prec == 0 ? GF_Q3(double) : GF_Q3(float);
 #undef GF_Q3
+    return e;
+}
+
+#ifndef GF_QSTREAM_T
+#define GF_QSTREAM_T 6
+#endif
+
+// Whether k_quality_tstream can take lattice g (single lattices only).
+bool quality_tstream_ok(const Geom &g) { return g.st % (QTILE / 2) == 0 && g.nt >= 2; }
+
+template <typename R, int NE>
+static hipError_t launch_qts(const Geom &g, const CfgDesc *d_desc, const int *d_active, double *d_partials,
+                             hipStream_t st) {
+    static_assert(GF_QSTREAM_T >= 1, "slices per run");
+    const int nchunk = g.st / (QTILE / 2);
+    const int trun = (g.nt + (g.nt + GF_QSTREAM_T - 1) / GF_QSTREAM_T - 1) /
+                     ((g.nt + GF_QSTREAM_T - 1) / GF_QSTREAM_T);  // <= GF_QSTREAM_T, runs as even as they go
+    const int runs = (g.nt + trun - 1) / trun;                        // each holds >= 1 slice
+    hipLaunchKernelGGL((k_quality_tstream<R, NE>), dim3(runs * nchunk), dim3(QTILE), 0, st, d_desc, d_active,
+                       nchunk, trun, d_partials);
+    return hipGetLastError();
+}
+
+hipError_t launch_quality_tstream(int prec, int nelem, const Geom &g, const CfgDesc *d_desc, const int *d_active,
+                                  double *d_partials, hipStream_t st) {
+    if (!quality_tstream_ok(g)) return hipErrorInvalidValue;
+#define GF_QTS(R)                                                                                 \
+    (nelem == 9   ? launch_qts<R, 9>(g, d_desc, d_active, d_partials, st)                          \
+     : nelem == 6 ? launch_qts<R, 6>(g, d_desc, d_active, d_partials, st)                          \
+                  : launch_qts<R, 4>(g, d_desc, d_active, d_partials, st))
+    const hipError_t e = prec == 0 ? GF_QTS(double) : GF_QTS(float);
+#undef GF_QTS
     return e;
 }
 

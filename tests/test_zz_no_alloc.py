@@ -1,8 +1,10 @@
 """gf_quality_noalloc (F and theta with no context and no allocation, for
 callers that cannot allocate) through the C ABI, against gf_quality on the
 same fields: the two share the reduction's tiles, order and normalisation, so
-the results must be bitwise equal. Two calls in a row, the second on a
-smaller lattice (the fixed scratch keeps the first call's partials), in both
+the results must be bitwise equal -- also where the context path takes the
+tiles in another order (2-d column blocks) or walks them slice by slice
+(double, Landau and Coulomb). Calls in a row, each later one on a smaller
+lattice (the fixed scratch keeps the earlier call's partials), in both
 precisions and all three storage forms, including the 48^4 FP32 field of the
 benchmark; plus the size limit and argument errors."""
 import ctypes
@@ -42,7 +44,10 @@ def field(gf, dims, gauge, prec, storage, amp, seed):
 @pytest.mark.parametrize("prec", [0, 1])
 def test_two_calls_match_gf_quality(gf, prec, storage):
     out = torch.full((2,), float("nan"), dtype=torch.float64, device="cuda")
-    for dims, gauge, seed in (((16, 16, 16, 24), COULOMB, 1), ((6, 4, 4, 2), LANDAU, 2)):
+    # (16, 16, 8, 14) Landau: in double the context path walks the 14 time
+    # slices in runs of 5, 5 and 4, passing t links between lanes
+    for dims, gauge, seed in (((16, 16, 16, 24), COULOMB, 1), ((16, 16, 8, 14), LANDAU, 3),
+                              ((6, 4, 4, 2), LANDAU, 2)):
         ctx, U = field(gf, dims, gauge, prec, storage, 0.6, seed)
         assert noalloc(gf, U, dims, gauge, prec, storage, out) == gf.OK, gf.lib.gf_last_error(None)
         got = tuple(out.cpu().tolist())
