@@ -218,6 +218,66 @@ def bw_reference(torch, nbytes, achieved_gbs):
     return res
 
 
+def run_fixed_sweeps(gf, torch, U64, dims, params, nsweep=500):
+    """Fixed sweep counts on the benchmark field: for omega 1.5, 1.7 and 1.9,
+    nsweep FP32 sweeps with no theta checks (reunitarisation fused every 10),
+    timed as one call after 10 untimed sweeps; FP64 at omega 1.7 beside it.
+    theta after the sweeps is read afterwards, outside the timed region."""
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    res = {"workload": f"SU(3) Landau, {'x'.join(map(str, dims))}, amp 0.7, seed 0, {nsweep} sweeps, "
+                       "reunitarisation every 10, no checks",
+           "sweeps": nsweep}
+    for name, prec, w in (("fp32_omega_1.5", gf.F32, 1.5), ("fp32_omega_1.7", gf.F32, 1.7),
+                          ("fp32_omega_1.9", gf.F32, 1.9), ("fp64_omega_1.7", gf.F64, 1.7)):
+        log(f"{nsweep} fixed sweeps, {name}")
+        ctx = gf.Context(dims, gauge=gf.LANDAU, prec=prec, params=params(prec, 0))
+        U = ctx.pack(U64 if prec == gf.F64 else U64.to(torch.complex64))
+        ctx.sweeps(U, w, 10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.sweeps(U, w, nsweep)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        F, th = ctx.quality(U)
+        res[name] = dict(seconds=sec, site_sweeps_per_s=V * nsweep / sec, F=F, theta_after=th)
+        del U, ctx
+        torch.cuda.empty_cache()
+    return res
+
+
+def run_slab_shape(gf, synth, torch, dims=(48, 48, 48, 12), nsweep=20):
+    """The half-sweep at 48^3x12, the share of one GPU if the 48^3x96
+    lattice were cut into eight slabs along t (the split is not built): the
+    kernel-only half-sweep time (HIP events, FP32 and FP64 18-real), beside
+    the size of the cut face's current-parity links that such a split would
+    send each way per half-sweep, and that message's time over one xGMI link
+    at its nominal 153 GB/s (an estimate, not a measurement)."""
+    V = dims[0] * dims[1] * dims[2] * dims[3]
+    face = dims[0] * dims[1] * dims[2] // 2
+    res = {"workload": "SU(3) Landau, 48x48x48x12, amp 0.6, seed 0, omega 1.7", "lattice": list(dims)}
+    U64 = synth.random_gauge_field(dims, 0.6, 0, device="cuda")
+    for name, prec in (("fp32", gf.F32), ("fp64", gf.F64)):
+        log(f"48^3x12 half-sweeps, {name}")
+        ctx = gf.Context(dims, gauge=gf.LANDAU, prec=prec,
+                         params=gf.default_params(prec, reunit_every=10, timing=1))
+        U = ctx.pack(U64 if prec == gf.F64 else U64.to(torch.complex64))
+        ctx.sweeps(U, 1.7, 4)
+        ctx.timing()
+        ctx.sweeps(U, 1.7, nsweep)
+        ms, nl = ctx.timing()
+        avg = ms / 1e3 / nl
+        lb = 18 * (4 if prec == gf.F32 else 8)
+        msg = face * lb
+        res[name] = dict(avg_halfsweep_us=avg * 1e6, site_sweeps_per_s=V / (2 * avg),
+                         achieved_gbs=16 * lb * (V // 2) / avg / 1e9,
+                         face_message_bytes=msg, face_message_us_at_153_gbs=msg / 153e9 * 1e6)
+        del U, ctx
+        torch.cuda.empty_cache()
+    del U64
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_diff(gf, synth, torch, sizes=(24, 48)):
     """Differentiation line: F_U[g] (gf_functional), its hand-written
     backward (gf_functional_grad) and the gauge transformation at L^4 for
@@ -415,6 +475,10 @@ def main():
     ap.add_argument("--no-ensemble", action="store_true",
                     help="skip the ensemble leg (Coulomb 48^3x96 + 64 uneven Landau lattices)")
     ap.add_argument("--no-diff", action="store_true", help="skip the differentiation timing leg")
+    ap.add_argument("--no-fixed-sweeps", action="store_true",
+                    help="skip the 500 fixed sweeps (no checks) at omega 1.5, 1.7, 1.9")
+    ap.add_argument("--no-slab", action="store_true",
+                    help="skip the half-sweep timing at 48^3x12 (one GPU's share of 48^3x96 split in eight)")
     ap.add_argument("--no-sun", action="store_true", help="skip the SU(2) / SU(4) leg")
     ap.add_argument("--no-bw-reference", action="store_true",
                     help="skip the device copy / in-place read-modify-write bandwidth reference")
@@ -657,6 +721,12 @@ def main():
         conv["abs_F_fp32_minus_fp64"] = abs(conv["fp32"]["F"] - conv["fp64"]["F"])
         conv["theta_convention"] = "literal eq. (3): A = M - M^+, minus trace/3, no 1/2 or 1/(2i)"
         out["convergence"] = conv
+
+    if not args.no_fixed_sweeps:
+        out["fixed_sweeps"] = run_fixed_sweeps(gf, torch, U64, dims, params)
+
+    if not args.no_slab:
+        out["slab_48x48x48x12"] = run_slab_shape(gf, synth, torch)
 
     if not args.no_diff:
         out["differentiation"] = run_diff(gf, synth, torch)
