@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ["sweep.hip", "su3_device.hpp", "gf_math.hpp", "gf_internal.hpp", "link8.hpp"]
+KERNEL_SOURCES = ["sweep.hip", "su3_device.hpp", "gf_math.hpp", "gf_internal.hpp", "link8.hpp", "tile_order.hpp"]
 
 
 def log(msg):

@@ -8,7 +8,7 @@ namespace gf {
 // Workgroups are dispatched to the 8 XCDs round-robin by id. Map id b of n
 // to a tile so that XCD k gets the k-th contiguous share of the tiles, in
 // order (a bijection of [0, n) for any n).
-__device__ __forceinline__ int xcd_tile(int b, int n) {
+__host__ __device__ __forceinline__ int xcd_tile(int b, int n) {
     constexpr int NX = 8;
     const int x = b % NX, i = b / NX;
     const int q = n / NX, r = n % NX;
@@ -106,7 +106,7 @@ inline SlabOrder pick_slab_order(int st, int sz, int hx, int nz, int tile_h, int
 }
 
 // Tile of sequence position q (a bijection of [0, ntiles)).
-__device__ __forceinline__ int slab_tile(int q, const SlabOrder &o) {
+__host__ __device__ __forceinline__ int slab_tile(int q, const SlabOrder &o) {
     if (o.S == 0) return q;
     const int m = o.nrow * o.S;
     if (q >= m) return q;
