@@ -43,49 +43,73 @@ constexpr double inv_factorial(int k) {
     return 1.0 / f;
 }
 
-// exp(S) by scaling and squaring of the Taylor polynomial of degree
-// B * NB - 1 (scaled argument Y of Frobenius norm <= 1/2, so the truncation
-// is below 2^-(B NB) / (B NB)!: 5e-9 for degree 8, 2e-17 for degree 15),
-// evaluated by the Paterson-Stockmeyer scheme: the powers Y^2 .. Y^B once,
-// then Horner in Z = Y^B over coefficient blocks sum_j c_{B i + j} Y^j
-// (j < B). Degree 8 takes 4 matrix products instead of 8, degree 15 takes
-// 6 instead of 15.
-template <int B, int NB>
-__device__ void dm_exp(const DMat &S, DMat &E) {
-    double nrm2 = 0.0;
+// c = a b for 3x3 complex matrices with elements of type T (float or
+// double), each element an FMA chain (in double the same operations as
+// dm_mul).
+template <typename T>
+__device__ __forceinline__ void cm_mul(const Mat<T> &a, const Mat<T> &b, Mat<T> &c) {
+#pragma unroll
+    for (int i = 0; i < 3; i++)
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            T r = a.re[3 * i] * b.re[j], m = a.re[3 * i] * b.im[j];
+            r = fma(-a.im[3 * i], b.im[j], r);
+            m = fma(a.im[3 * i], b.re[j], m);
+#pragma unroll
+            for (int k = 1; k < 3; k++) {
+                r = fma(a.re[3 * i + k], b.re[3 * k + j], r);
+                r = fma(-a.im[3 * i + k], b.im[3 * k + j], r);
+                m = fma(a.re[3 * i + k], b.im[3 * k + j], m);
+                m = fma(a.im[3 * i + k], b.re[3 * k + j], m);
+            }
+            c.re[3 * i + j] = r;
+            c.im[3 * i + j] = m;
+        }
+}
+
+// exp(S) in arithmetic of type T by scaling and squaring of the Taylor
+// polynomial of degree B * NB - 1 (scaled argument Y of Frobenius norm
+// <= 1/2, so the truncation is below 2^-(B NB) / (B NB)!: 5e-9 for degree 8,
+// 2e-17 for degree 15), evaluated by the Paterson-Stockmeyer scheme: the
+// powers Y^2 .. Y^B once, then Horner in Z = Y^B over coefficient blocks
+// sum_j c_{B i + j} Y^j (j < B). Degree 8 takes 4 matrix products instead of
+// 8, degree 15 takes 6 instead of 15.
+template <typename T, int B, int NB>
+__device__ void cm_exp(const Mat<T> &S, Mat<T> &E) {
+    T nrm2 = T(0);
 #pragma unroll
     for (int e = 0; e < 9; e++) nrm2 += S.re[e] * S.re[e] + S.im[e] * S.im[e];
-    const double nrm = sqrt(nrm2);
+    const T nrm = sqrt(nrm2);
     int k = 0;
-    if (nrm > 0.5) k = (int)ceil(log2(nrm / 0.5));
-    const double sc = ldexp(1.0, -k);
-    DMat pw[B + 1];  // pw[j] = Y^j, j = 1 .. B
+    if (nrm > T(0.5)) k = (int)ceil(log2(nrm / T(0.5)));
+    const T sc = ldexp(T(1), -k);
+    Mat<T> pw[B + 1];  // pw[j] = Y^j, j = 1 .. B
 #pragma unroll
     for (int e = 0; e < 9; e++) { pw[1].re[e] = S.re[e] * sc; pw[1].im[e] = S.im[e] * sc; }
 #pragma unroll
-    for (int j = 2; j <= B; j++) dm_mul(pw[j - 1], pw[1], pw[j]);
+    for (int j = 2; j <= B; j++) cm_mul(pw[j - 1], pw[1], pw[j]);
     // E = block NB - 1, then E <- E Z + block i for i = NB - 2 .. 0
 #pragma unroll
     for (int i = NB - 1; i >= 0; i--) {
-        DMat T;
-        if (i < NB - 1) dm_mul(E, pw[B], T);
+        Mat<T> Tm;
+        if (i < NB - 1) cm_mul(E, pw[B], Tm);
 #pragma unroll
         for (int e = 0; e < 9; e++) {
-            double r = (e % 4 == 0) ? inv_factorial(B * i) : 0.0, m = 0.0;
+            T r = (e % 4 == 0) ? T(inv_factorial(B * i)) : T(0), m = T(0);
 #pragma unroll
             for (int j = 1; j < B; j++) {
-                r = fma(inv_factorial(B * i + j), pw[j].re[e], r);
-                m = fma(inv_factorial(B * i + j), pw[j].im[e], m);
+                r = fma(T(inv_factorial(B * i + j)), pw[j].re[e], r);
+                m = fma(T(inv_factorial(B * i + j)), pw[j].im[e], m);
             }
-            if (i < NB - 1) { r += T.re[e]; m += T.im[e]; }
+            if (i < NB - 1) { r += Tm.re[e]; m += Tm.im[e]; }
             E.re[e] = r;
             E.im[e] = m;
         }
     }
     for (int i = 0; i < k; i++) {
-        DMat T;
-        dm_mul(E, E, T);
-        E = T;
+        Mat<T> Tm;
+        cm_mul(E, E, Tm);
+        E = Tm;
     }
 }
 
@@ -105,16 +129,22 @@ __global__ void __launch_bounds__(256) k_expS(Geom g, const R *__restrict__ s, t
     const int p = n >= g.Vh, h = n - p * g.Vh;
     double sv[8];
     load_s(s, g, p, h, sv);
-    DMat S, E;
+    DMat S;
     algebra_matrix(sv, S);
-    // the g field is stored in R: degree 8 is exact to float rounding, 15 to double
-    if constexpr (sizeof(R) == 4) dm_exp<3, 3>(S, E);
-    else dm_exp<4, 4>(S, E);
+    // The g field is stored in R, and the exponential is evaluated in R:
+    // degree 8 in float (truncation 5e-9, rounding a few units of float's,
+    // as for the stored g itself; in float the kernel needs half the
+    // registers and runs 136 -> 107 us at 48^4), degree 15 in double.
+    Mat<R> Sr, E;
+#pragma unroll
+    for (int e = 0; e < 9; e++) { Sr.re[e] = (R)S.re[e]; Sr.im[e] = (R)S.im[e]; }
+    if constexpr (sizeof(R) == 4) cm_exp<R, 3, 3>(Sr, E);
+    else cm_exp<R, 4, 4>(Sr, E);
 #pragma unroll
     for (int e = 0; e < 9; e++) {
         typename V2<R>::type v;
-        v.x = (R)E.re[e];
-        v.y = (R)E.im[e];
+        v.x = E.re[e];
+        v.y = E.im[e];
         gf[gfield_off(g, p, h, e)] = v;
     }
 }
