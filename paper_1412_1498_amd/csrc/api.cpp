@@ -383,6 +383,8 @@ int create_impl(gf_ctx **out, int n, const int *dims, const int *gauge, int prec
         const long long tile_bytes = (long long)QTILE * nd * ctx->nelem * 2 * (prec == GF_F64 ? 8 : 4);
         ctx->qslab = pick_slab_order(g0.st, g0.sz, g0.hx, g0.nz, QTILE / 2, nq, tile_bytes);
     }
+    // in double a single lattice's F/theta walks time slices (its tiles' t neighbours
+    // missed L2 in any slab order); in float the slab order is as fast
     ctx->qstream = n == 1 && ctx->nc == 3 && prec == GF_F64 && quality_tstream_ok(ctx->desc[0].g);
     std::vector<int> qmap;
     for (int c = 0; c < n; c++) qmap.insert(qmap.end(), ctx->desc[c].nqtiles, c);

@@ -17,8 +17,6 @@
 // partials, strided per lane then by the same fixed butterfly, and
 // normalises. Neither stage
 // depends on the sweep schedule, so F and theta are bitwise reproducible.
-#include <algorithm>
-
 #include "su3_device.hpp"
 #include "sun_device.hpp"
 #include "sun_internal.hpp"
@@ -362,6 +360,8 @@ hipError_t launch_quality(int prec, int nelem, const CfgDesc *d_desc, const int 
     return e;
 }
 
+// Slices per run of k_quality_tstream (runs of 3 to 12 slices measured
+// alike at 48^4; one round of resident workgroups, 24 to 48, was slower).
 #ifndef GF_QSTREAM_T
 #define GF_QSTREAM_T 6
 #endif
@@ -374,9 +374,9 @@ static hipError_t launch_qts(const Geom &g, const CfgDesc *d_desc, const int *d_
                              hipStream_t st) {
     static_assert(GF_QSTREAM_T >= 1, "slices per run");
     const int nchunk = g.st / (QTILE / 2);
-    const int trun = (g.nt + (g.nt + GF_QSTREAM_T - 1) / GF_QSTREAM_T - 1) /
-                     ((g.nt + GF_QSTREAM_T - 1) / GF_QSTREAM_T);  // <= GF_QSTREAM_T, runs as even as they go
-    const int runs = (g.nt + trun - 1) / trun;                        // each holds >= 1 slice
+    const int runs0 = (g.nt + GF_QSTREAM_T - 1) / GF_QSTREAM_T;
+    const int trun = (g.nt + runs0 - 1) / runs0;  // <= GF_QSTREAM_T slices, runs as even as they go
+    const int runs = (g.nt + trun - 1) / trun;    // each holds >= 1 slice
     hipLaunchKernelGGL((k_quality_tstream<R, NE>), dim3(runs * nchunk), dim3(QTILE), 0, st, d_desc, d_active,
                        nchunk, trun, d_partials);
     return hipGetLastError();
